@@ -1,0 +1,175 @@
+"""Boundary-MPS cache build (oracle side, float64, dense).
+
+Test infrastructure only: nothing in the product path imports this module.
+
+Follows section 3.2 (cache initialization) and section 2.2 (Eqs. (6)-(8),
+Fig. 2) step by step, with plain dense tensors:
+
+1. bottom row L-1: copy tensors combined with that row's horizontal
+   Boltzmann matrices give a bond-dimension-2 MPS (site shapes (1,2,2),
+   (2,2,2), ..., (2,2,1));
+2. for each row r = L-2 ... 0: build the row MPO from copy tensors and the
+   row's right/down Boltzmann matrices (index order left, phys, right, down;
+   shapes (1,2,2,2), (2,2,2,2), ..., (2,2,1,2)); apply it to the MPS
+   ("multiply", which doubles the bond); truncate back to chi ("compress").
+
+``compress`` is not listed in the paper; the reading used here (and by the
+GPU path) is: a left-to-right QR sweep that makes every site left-canonical
+(exact, no truncation), then a right-to-left SVD sweep that at each bond keeps
+the min(chi, rank-bound) largest singular values, with no relative cutoff.
+Every norm taken out is accumulated in a float64 log-scale, so that
+
+    ln Z_TN = sum_r logscale[r] + ln( prod_c sum_s A^(0)_c[:, s, :] ).
+
+The cache row r represents, up to the scale exp(sum_{r' >= r} logscale[r']),
+the function of row r's spins  psi_r(s_r) = sum over rows > r of
+exp(-beta * E(rows >= r)), i.e. it includes row r's horizontal bonds and every
+vertical bond below row r (exactly when chi >= 2**floor(L/2)).
+
+Pins (tests/test_oracle_bmps.py): brute-force ln Z on 3x3/4x4, the dense
+transfer vector (exact and with the same sequential truncation) on L <= 10,
+closed forms (J_v = 0, J_h = 0, beta = 0) at large L, Z2 and gauge invariance.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .ising import boltzmann_matrix
+
+
+def copy_tensor(rank: int) -> np.ndarray:
+    """Eq. (8): the Kronecker delta with `rank` legs of dimension 2."""
+    t = np.zeros((2,) * rank)
+    for i in range(2):
+        t[(i,) * rank] = 1.0
+    return t
+
+
+def _normalise(t: np.ndarray):
+    nu = float(np.linalg.norm(t))
+    return t / nu, math.log(nu)
+
+
+def bottom_row_mps(beta: float, J_h: np.ndarray):
+    """Row L-1 of the cache, bond dimension 2 (section 3.2)."""
+    L = J_h.shape[0]
+    I2, I3 = np.eye(2), copy_tensor(3)
+    mps = [(I2 @ boltzmann_matrix(beta, J_h[L - 1, 0]))[None]]            # (1, 2, 2)
+    for c in range(1, L - 1):
+        mps.append(np.einsum("ask,kb->asb", I3, boltzmann_matrix(beta, J_h[L - 1, c])))
+    mps.append(I2[:, :, None])                                             # (2, 2, 1)
+    # Scale each site to unit norm; the state changes only by a positive
+    # factor, which is kept in the log-scale.
+    logscale = 0.0
+    for c in range(L):
+        mps[c], ln = _normalise(mps[c])
+        logscale += ln
+    return mps, logscale
+
+
+def row_mpo(beta: float, J_h: np.ndarray, J_v: np.ndarray, row: int):
+    """Row MPO from copy tensors and Boltzmann matrices (section 3.2).
+
+    Index order (left, phys, right, down).  The right leg carries the
+    horizontal Boltzmann matrix to the next column, the down leg the vertical
+    one to the row below.
+    """
+    L = J_h.shape[0]
+    I3, I4 = copy_tensor(3), copy_tensor(4)
+    mpo = []
+    Br, Bd = boltzmann_matrix(beta, J_h[row, 0]), boltzmann_matrix(beta, J_v[row, 0])
+    mpo.append(np.einsum("ijk,jl,km->ilm", I3, Br, Bd)[None])              # (1, 2, 2, 2)
+    for c in range(1, L - 1):
+        Br, Bd = boltzmann_matrix(beta, J_h[row, c]), boltzmann_matrix(beta, J_v[row, c])
+        mpo.append(np.einsum("ijkl,km,ln->ijmn", I4, Br, Bd))              # (2, 2, 2, 2)
+    Bd = boltzmann_matrix(beta, J_v[row, L - 1])
+    mpo.append(np.einsum("ijk,kl->ijl", I3, Bd)[:, :, None, :])            # (2, 2, 1, 2)
+    return mpo
+
+
+def multiply(mpo, mps):
+    """MPO x MPS: new[(a,l), s, (b,r)] = sum_n W[l, s, r, n] A[a, n, b]."""
+    out = []
+    for W, A in zip(mpo, mps):
+        Dl, _, Dr = A.shape
+        wl, _, wr, _ = W.shape
+        t = np.einsum("lsrn,anb->alsbr", W, A)
+        out.append(t.reshape(Dl * wl, 2, Dr * wr))
+    return out
+
+
+def compress(mps, chi: int):
+    """QR sweep left->right, then truncating SVD sweep right->left.
+
+    Returns (log of the norms taken out, new list of sites).  Bond c|c+1 ends
+    with dimension min(chi, rank bound); the singular values kept are the
+    largest ones, with no cutoff.
+    """
+    mps = [t.copy() for t in mps]
+    L = len(mps)
+    logn = 0.0
+    for c in range(L - 1):
+        Dl, d, Dr = mps[c].shape
+        Q, R = np.linalg.qr(mps[c].reshape(Dl * d, Dr), mode="reduced")
+        R, ln = _normalise(R)
+        logn += ln
+        mps[c] = Q.reshape(Dl, d, Q.shape[1])
+        mps[c + 1] = np.tensordot(R, mps[c + 1], axes=(1, 0))
+    mps[L - 1], ln = _normalise(mps[L - 1])
+    logn += ln
+    for c in range(L - 1, 0, -1):
+        Dl, d, Dr = mps[c].shape
+        U, S, Vt = np.linalg.svd(mps[c].reshape(Dl, d * Dr), full_matrices=False)
+        k = min(chi, S.shape[0])
+        U, S, Vt = U[:, :k], S[:k], Vt[:k]
+        nrm = float(np.linalg.norm(S))
+        logn += math.log(nrm)
+        mps[c] = Vt.reshape(k, d, Dr)
+        mps[c - 1] = np.tensordot(mps[c - 1], U * (S / nrm), axes=(2, 0))
+    mps[0], ln = _normalise(mps[0])
+    logn += ln
+    return logn, mps
+
+
+def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int):
+    """The full cache for one instance.
+
+    Returns (cache, logscale, logZ) where cache[r] is the list of row r's
+    site tensors (shapes (Dl, 2, Dr), normalised), logscale[r] the log of the
+    norms taken out when row r was formed, and logZ the TN estimate of ln Z.
+    """
+    J_h = np.asarray(J_h, dtype=np.float64)
+    J_v = np.asarray(J_v, dtype=np.float64)
+    L = J_h.shape[0]
+    cache = [None] * L
+    logscale = np.zeros(L)
+    mps, logscale[L - 1] = bottom_row_mps(beta, J_h)
+    cache[L - 1] = mps
+    for row in range(L - 2, -1, -1):
+        mps = multiply(row_mpo(beta, J_h, J_v, row), mps)
+        logscale[row], mps = compress(mps, chi)
+        cache[row] = mps
+    return cache, logscale, float(logscale.sum() + log_total(cache[0]))
+
+
+def log_total(mps) -> float:
+    """ln of the MPS contracted with every physical index summed."""
+    v = np.ones(1)
+    lsum = 0.0
+    for A in mps:
+        v = v @ A.sum(axis=1)
+        n = float(np.abs(v).max())
+        v = v / n
+        lsum += math.log(n)
+    return lsum + math.log(float(v[0]))
+
+
+def mps_to_dense(mps) -> np.ndarray:
+    """Dense 2**L vector of an MPS, spin index 0 of site 0 most significant."""
+    v = mps[0].reshape(2, -1)
+    for A in mps[1:]:
+        Dl, _, Dr = A.shape
+        v = (v @ A.reshape(Dl, 2 * Dr)).reshape(-1, Dr)
+    return v.reshape(-1)
