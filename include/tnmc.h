@@ -1,0 +1,194 @@
+/*
+ * tnmc.h -- batched tensor-network Monte Carlo (TNMC) for 2D Ising spin
+ * glasses on AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv 2509.19006, "BatchTNMC"):
+ *   1. tnmc_build_env  -- boundary-MPS cache: starting from the bottom row,
+ *      apply each row's transfer MPO to the boundary MPS and truncate back to
+ *      bond dimension chi (section 2.2, Fig. 2; section 3.2);
+ *   2. tnmc_sample     -- row-by-row autoregressive sampling from the cached
+ *      environments (section 3.3, Eqs. (3)-(5));
+ *   3. tnmc_energy     -- exact energies, Eq. (1);
+ *   4. tnmc_accept     -- Metropolis independence accept/reject, Eq. (10).
+ * Every call is batched over disorder instances x samples (section 3.4).
+ *
+ * Conventions shared by every entry point
+ *  - Lattice: open L x L square lattice.  J_h[r][c] couples (r,c)-(r,c+1)
+ *    (shape L x (L-1), row-major); J_v[r][c] couples (r,c)-(r+1,c) (shape
+ *    (L-1) x L).  Each bond appears once.  Spins are -1/+1.
+ *  - Spins are bit-packed: instance i, sample n, row r is W_i = ceil(L_i/64)
+ *    uint64 words; bit (c mod 64) of word c/64 is 1 iff spin (r,c) is +1.
+ *    Instances follow each other in batch order, samples within an
+ *    instance, rows within a sample:  word offset of (i, n, r) =
+ *    n_samples * sum_{j<i} L_j*W_j + (n*L_i + r)*W_i.
+ *  - Per-sample outputs (log q, energies, accept flags) are [batch][n_samples].
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are read during the call only.  The library never allocates
+ *    device memory: caches and scratch live in a caller-provided workspace.
+ *  - `stream` is a hipStream_t passed as void*; all device work is enqueued
+ *    on it and the call returns without synchronising.  The caller keeps
+ *    device buffers alive until that work completes.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *    (seed & 0xffffffff, seed >> 32).  Site draw of sample n (global index,
+ *    i.e. sample_offset + n) at site (r,c) of instance i uses counter
+ *    (r*L_i + c, n, i, 0); the accept draw of proposal k uses (k, 0, i, 1).
+ *    The uniform is ((w0>>5)*2^26 + (w1>>6)) * 2^-53 and a spin is +1 iff
+ *    uniform < p(+1).
+ *  - Errors: every int-returning function returns TNMC_OK (0) or a
+ *    negative TNMC_E* code; tnmc_last_error() then describes it (thread
+ *    local).  Arguments are validated before any device work is enqueued;
+ *    on error nothing is enqueued and outputs are untouched.  Errors of
+ *    already-enqueued device work (TNMC_EHIP) surface at a later call.
+ */
+#ifndef TNMC_H
+#define TNMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define TNMC_OK        0
+#define TNMC_EINVAL   -1   /* bad shape, chi, beta, null pointer, count     */
+#define TNMC_ENOSPACE -2   /* workspace smaller than tnmc_workspace_size    */
+#define TNMC_EHIP     -3   /* HIP runtime or launch error                   */
+#define TNMC_ENOTSUP  -4   /* precision / size combination not built        */
+
+/* ---- precision of the boundary-MPS build and of the sampler ----------- */
+#define TNMC_FP64        0 /* everything in float64                          */
+#define TNMC_FP32        1 /* contractions, QR, SVD and cache in float32;    */
+                           /* log-weights, log q and accept in float64       */
+#define TNMC_MIXED_BF16  2 /* build in float32, cache stored in bfloat16,   */
+                           /* sampler contractions bf16 x bf16 -> float32    */
+#define TNMC_MIXED_FP16  3 /* as MIXED_BF16 with float16 cache storage       */
+
+/* largest bond dimension and lattice side the kernels are built for */
+#define TNMC_CHI_MAX  64
+#define TNMC_L_MAX    1024
+
+/* Problem description: a batch of independent instances (section 3.4).   */
+typedef struct tnmc_problem {
+    int32_t        batch;   /* number of instances B >= 1                     */
+    const int32_t *L;       /* host [B]   lattice side, 2 <= L_i <= TNMC_L_MAX */
+    const int32_t *chi;     /* host [B]   bond dimension, 2 <= chi_i <= 64    */
+    const double  *beta;    /* host [B]   inverse temperature, finite, >= 0   */
+    const float   *J_h;     /* device     horizontal couplings, see above     */
+    const float   *J_v;     /* device     vertical couplings                  */
+    const int64_t *off_h;   /* host [B] or NULL: element offset of instance i */
+    const int64_t *off_v;   /*   in J_h / J_v; NULL = packed in batch order   */
+} tnmc_problem;
+
+/* Per-instance Metropolis chain state (device memory, caller owned).
+ * Zero-fill before the first tnmc_accept call of a chain.                */
+typedef struct tnmc_chain {
+    double  cur_logq;       /* log q of the current state                    */
+    double  cur_E;          /* energy of the current state                   */
+    int64_t cur_index;      /* global proposal index of the current state    */
+    int64_t n_acc;          /* accepted trials so far                        */
+    int64_t n_trials;       /* trials so far (the initialising proposal is   */
+                            /* not a trial)                                  */
+    int64_t initialised;    /* 0 until the first proposal has been taken     */
+} tnmc_chain;
+
+typedef struct tnmc_env tnmc_env;   /* opaque; host metadata into workspace */
+
+/* Learned proposal correction: a 3-layer tanh MLP (width 64) whose output is
+ * added to every site's TN logit.  Weights are device float32 arrays, row
+ * major [out][in]; layer 1 takes TNMC_MLP_IN features (see tnmc_sample).   */
+#define TNMC_MLP_IN     64
+#define TNMC_MLP_HIDDEN 64
+typedef struct tnmc_mlp {
+    const float *W1, *b1;   /* [64][64], [64] */
+    const float *W2, *b2;   /* [64][64], [64] */
+    const float *W3, *b3;   /* [64],     [1]  */
+} tnmc_mlp;
+
+/* Bytes of workspace tnmc_build_env + tnmc_sample need for this problem at
+ * this precision with up to max_samples samples per instance per call.
+ * Returns TNMC_EINVAL on a bad problem.                                    */
+int tnmc_workspace_size(const tnmc_problem *p, int32_t precision,
+                        int32_t max_samples, size_t *bytes_out);
+
+/* Build the boundary-MPS cache of every instance (sections 2.2 and 3.2).
+ *  workspace  device, >= tnmc_workspace_size bytes, 256-byte aligned; the
+ *             cache lives there until the env is freed or rebuilt.
+ *  logz_out   device double [B] or NULL: the tensor-network estimate of
+ *             ln Z (exact when chi_i >= 2^floor(L_i/2)).
+ *  env_out    receives a new env (free with tnmc_free_env).  It keeps copies
+ *             of the host arrays of *p and the device pointers J_h / J_v,
+ *             which must stay valid while the env is used.
+ * The compression is a left-to-right QR sweep followed by a right-to-left
+ * truncating SVD sweep keeping the chi largest singular values per bond. */
+int tnmc_build_env(const tnmc_problem *p, int32_t precision,
+                   void *workspace, size_t workspace_bytes, void *stream,
+                   tnmc_env **env_out, double *logz_out);
+
+/* Draw (or score) n_samples configurations per instance (section 3.3).
+ *  seed, sample_offset  Philox key and first global sample index.
+ *  forced_spins  device, NULL to sample; otherwise configurations in the
+ *                packed layout to be scored (teacher forcing): the sampler
+ *                evaluates their log q and logits instead of drawing.
+ *  mlp           NULL for the plain TN proposal, else the learned
+ *                correction added to every logit before the draw.
+ *  spins_out     device uint64, packed layout (may equal forced_spins).
+ *  logq_out      device double [B][n_samples]: log q of each configuration.
+ *  logits_out    device float [B][n_samples][L_i*L_i] or NULL: the logit of
+ *                p(+1) at every site (after the MLP correction if any).
+ * n_samples must not exceed the max_samples the workspace was sized for.  */
+int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed,
+                uint64_t sample_offset, const uint64_t *forced_spins,
+                const tnmc_mlp *mlp, uint64_t *spins_out, double *logq_out,
+                float *logits_out, void *stream);
+
+/* Exact energies E(s) = -sum J s s over every bond once (Eq. (1)) of the
+ * instances the env was built for (its couplings and sizes).
+ *  spins   device, packed layout for n_samples per instance.
+ *  E_out   device double [B][n_samples].  Exact for +-1 couplings and for
+ *          couplings on the 2^-20 grid with |J| < 8.                       */
+int tnmc_energy(const tnmc_env *env, int32_t n_samples, const uint64_t *spins,
+                double *E_out, void *stream);
+
+/* Metropolis independence step over each instance's proposals in index
+ * order (Eq. (10)): with current state x and candidate k,
+ *   delta = (logq_x - logq_k) + beta * (E_x - E_k)   (no fused operations)
+ * and k is accepted iff delta >= 0 or u_k < exp(delta).  On a chain's first
+ * call its first proposal initialises it (flag 1, not a trial).
+ *  logq, E      device double [batch][n_samples]
+ *  beta         device double [batch]
+ *  chain        device tnmc_chain [batch], updated in place
+ *  step_offset  global index of this call's first proposal (Philox counter)
+ *  accepted_out device uint8 [batch][n_samples] (1 = accepted)
+ *  state_out    device int64 [batch][n_samples]: global index of the chain
+ *               state after each proposal (NULL allowed).                  */
+int tnmc_accept(int32_t batch, int32_t n_samples, const double *logq,
+                const double *E, const double *beta, tnmc_chain *chain,
+                uint64_t seed, uint64_t step_offset, uint8_t *accepted_out,
+                int64_t *state_out, void *stream);
+
+/* Release an env (host memory only; the workspace stays the caller's).    */
+void tnmc_free_env(tnmc_env *env);
+
+/* Description of the last error on this thread ("" if none).             */
+const char *tnmc_last_error(void);
+
+/* Philox uniforms for counters (c0[k], c1, c2, stream) under key(seed),
+ * written to out[k] (device double [n]); c0 is a device uint32 [n].  The
+ * same generator the sampler and the accept step draw from.               */
+int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
+                        uint32_t c2, uint32_t stream_id, int32_t n,
+                        double *out, void *stream);
+
+/* Build statistics of this env (device int64 [B][4], valid once the build
+ * has completed on its stream): per instance the total number of Jacobi
+ * sweeps over all truncations, then the wall-clock ticks (100 MHz device
+ * counter) spent in the QR sweeps, in the SVD sweeps, and inside the Jacobi
+ * iterations of those SVD sweeps.  NULL for a NULL env.                    */
+const int64_t *tnmc_env_stats(const tnmc_env *env);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNMC_H */

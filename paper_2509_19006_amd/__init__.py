@@ -1,0 +1,208 @@
+"""Batched tensor-network Monte Carlo (TNMC) on MI355X -- Python binding.
+
+A thin ctypes layer over the C ABI in include/tnmc.h.  Functions carry the
+same names as the C entry points and only marshal arguments: torch tensors
+provide device memory and the current HIP stream; every step of the method
+runs in the HIP kernels of libtnmc.so.  If the library is missing the calls
+raise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so")
+
+TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP = 0, -1, -2, -3, -4
+FP64, FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
+CHAIN_BYTES = 48           # sizeof(tnmc_chain)
+
+_lib = None
+
+
+class TnmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tnmc error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("batch", c_int32), ("L", POINTER(c_int32)), ("chi", POINTER(c_int32)),
+                ("beta", POINTER(c_double)), ("J_h", c_void_p), ("J_v", c_void_p),
+                ("off_h", POINTER(c_int64)), ("off_v", POINTER(c_int64))]
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("W1", c_void_p), ("b1", c_void_p), ("W2", c_void_p), ("b2", c_void_p),
+                ("W3", c_void_p), ("b3", c_void_p)]
+
+
+EXPORTS = ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy", "tnmc_accept",
+           "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats")
+
+
+def load(path: str = LIB_PATH):
+    """Load libtnmc.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise TnmcError(TNMC_EHIP, f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = POINTER
+    lib.tnmc_workspace_size.argtypes = [P(_Problem), c_int32, c_int32, P(c_size_t)]
+    lib.tnmc_build_env.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p), c_void_p]
+    lib.tnmc_sample.argtypes = [c_void_p, c_int32, c_uint64, c_uint64, c_void_p, P(_Mlp), c_void_p,
+                                c_void_p, c_void_p, c_void_p]
+    lib.tnmc_energy.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.tnmc_accept.argtypes = [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint64,
+                                c_uint64, c_void_p, c_void_p, c_void_p]
+    lib.tnmc_free_env.argtypes = [c_void_p]
+    lib.tnmc_free_env.restype = None
+    lib.tnmc_last_error.restype = ctypes.c_char_p
+    lib.tnmc_philox_uniform.argtypes = [c_uint64, c_void_p, c_uint32, c_uint32, c_uint32, c_int32,
+                                        c_void_p, c_void_p]
+    lib.tnmc_env_stats.argtypes = [c_void_p]
+    lib.tnmc_env_stats.restype = c_void_p
+    for name in ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy",
+                 "tnmc_accept", "tnmc_philox_uniform"):
+        getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != TNMC_OK:
+        raise TnmcError(rc, _lib.tnmc_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """Host-side problem description; J_h / J_v are device float32 tensors.
+
+    Either uniform: J_h (B, L, L-1), J_v (B, L-1, L) with scalar or per-instance
+    chi/beta; or uneven: flat J_h / J_v with per-instance L and offsets.
+    """
+
+    def __init__(self, J_h, J_v, L, chi, beta, off_h=None, off_v=None):
+        import numpy as np
+        self.J_h, self.J_v = J_h, J_v
+        B = len(L)
+        self.L = np.ascontiguousarray(L, dtype=np.int32)
+        self.chi = np.ascontiguousarray(np.broadcast_to(chi, (B,)), dtype=np.int32)
+        self.beta = np.ascontiguousarray(np.broadcast_to(beta, (B,)), dtype=np.float64)
+        self.off_h = None if off_h is None else np.ascontiguousarray(off_h, dtype=np.int64)
+        self.off_v = None if off_v is None else np.ascontiguousarray(off_v, dtype=np.int64)
+        self.batch = B
+        self._c = _Problem(
+            B, self.L.ctypes.data_as(POINTER(c_int32)), self.chi.ctypes.data_as(POINTER(c_int32)),
+            self.beta.ctypes.data_as(POINTER(c_double)),
+            None if J_h is None else J_h.data_ptr(), None if J_v is None else J_v.data_ptr(),
+            None if self.off_h is None else self.off_h.ctypes.data_as(POINTER(c_int64)),
+            None if self.off_v is None else self.off_v.ctypes.data_as(POINTER(c_int64)))
+
+    @classmethod
+    def uniform(cls, J_h, J_v, chi, beta):
+        B, L = J_h.shape[0], J_h.shape[1]
+        return cls(J_h, J_v, [L] * B, chi, beta)
+
+    def words(self):
+        return [(int(L) + 63) // 64 for L in self.L]
+
+    def spin_words_per_sample(self):
+        return sum(int(L) * w for L, w in zip(self.L, self.words()))
+
+
+def tnmc_workspace_size(problem: Problem, precision: int, max_samples: int) -> int:
+    lib = load()
+    out = c_size_t(0)
+    _check(lib.tnmc_workspace_size(byref(problem._c), precision, max_samples, byref(out)))
+    return out.value
+
+
+class Env:
+    def __init__(self, handle, problem, precision, workspace):
+        self.handle, self.problem, self.precision, self.workspace = handle, problem, precision, workspace
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tnmc_free_env(self.handle)
+            self.handle = None
+
+
+def tnmc_build_env(problem: Problem, precision: int, workspace, logz_out=None, stream=None) -> Env:
+    """Build every instance's boundary-MPS cache into `workspace` (a uint8
+    device tensor of at least tnmc_workspace_size bytes)."""
+    lib = load()
+    h = c_void_p(0)
+    _check(lib.tnmc_build_env(byref(problem._c), precision, _ptr(workspace), workspace.numel(),
+                              _stream(stream), byref(h), _ptr(logz_out)))
+    return Env(h, problem, precision, workspace)
+
+
+def tnmc_sample(env: Env, n_samples: int, seed: int, spins_out, logq_out, sample_offset: int = 0,
+                forced_spins=None, mlp=None, logits_out=None, stream=None):
+    lib = load()
+    m = None
+    if mlp is not None:
+        m = _Mlp(*(t.data_ptr() for t in mlp))
+    _check(lib.tnmc_sample(env.handle, n_samples, seed, sample_offset, _ptr(forced_spins),
+                           None if m is None else byref(m), _ptr(spins_out), _ptr(logq_out),
+                           _ptr(logits_out), _stream(stream)))
+
+
+def tnmc_energy(env: Env, n_samples: int, spins, E_out, stream=None):
+    lib = load()
+    _check(lib.tnmc_energy(env.handle, n_samples, _ptr(spins), _ptr(E_out), _stream(stream)))
+
+
+def tnmc_accept(logq, E, beta, chain, seed: int, step_offset: int, accepted_out, state_out=None,
+                stream=None):
+    """logq, E: (B, N) float64; beta: (B,) float64; chain: uint8 (B*48,) zero-
+    initialised device tensor; accepted_out uint8 (B, N); state_out int64."""
+    lib = load()
+    B, N = logq.shape
+    _check(lib.tnmc_accept(B, N, _ptr(logq), _ptr(E), _ptr(beta), _ptr(chain), seed, step_offset,
+                           _ptr(accepted_out), _ptr(state_out), _stream(stream)))
+
+
+def tnmc_philox_uniform(seed: int, c0, c1: int, c2: int, stream_id: int, out, stream=None):
+    lib = load()
+    _check(lib.tnmc_philox_uniform(seed, _ptr(c0), c1, c2, stream_id, c0.numel(), _ptr(out),
+                                   _stream(stream)))
+
+
+def tnmc_env_stats(env: Env):
+    """Build statistics as a host int64 array (B, 4): Jacobi sweeps, then
+    100 MHz ticks in the QR sweeps, the SVD sweeps and the Jacobi loops.
+    Synchronises the current stream."""
+    import numpy as np
+    import torch
+    addr = load().tnmc_env_stats(env.handle)
+    off = addr - env.workspace.data_ptr()
+    torch.cuda.current_stream().synchronize()
+    return env.workspace[off:off + 32 * env.problem.batch].view(torch.int64).cpu().numpy().reshape(-1, 4)
+
+
+def chain_state(chain_bytes):
+    """Decode a host copy of the chain array into a list of dicts."""
+    import numpy as np
+    raw = np.frombuffer(bytes(chain_bytes), dtype=np.uint8).reshape(-1, CHAIN_BYTES)
+    out = []
+    for row in raw:
+        f = np.frombuffer(row[:16].tobytes(), dtype=np.float64)
+        i = np.frombuffer(row[16:].tobytes(), dtype=np.int64)
+        out.append(dict(cur_logq=f[0], cur_E=f[1], cur_index=int(i[0]), n_acc=int(i[1]),
+                        n_trials=int(i[2]), initialised=int(i[3])))
+    return out

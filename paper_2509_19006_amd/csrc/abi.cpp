@@ -1,0 +1,295 @@
+// C ABI of the TNMC library: argument validation, workspace layout and
+// kernel dispatch.  No device memory is allocated here; every buffer lives
+// in the caller's workspace or in caller-owned arrays.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tnmc.h"
+#include "device.hpp"
+
+namespace tnmc {
+struct MlpArgs {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    const float *Jh;
+};
+template <typename T, typename S>
+hipError_t launch_build(const InstDesc *, unsigned char *, const float *, const float *, double *,
+                        int64_t *, int, size_t, hipStream_t);
+size_t build_lds_bytes(int chi, int L, size_t tsize);
+template <typename T, typename S>
+hipError_t launch_sample(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
+                         uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *,
+                         MlpArgs, hipStream_t);
+hipError_t launch_energy(const InstDesc *, int, int, const uint64_t *, const float *, const float *,
+                         double *, hipStream_t);
+hipError_t launch_accept(int, int, const double *, const double *, const double *, void *, uint64_t,
+                         uint64_t, uint8_t *, int64_t *, hipStream_t);
+hipError_t launch_philox(uint64_t, const uint32_t *, uint32_t, uint32_t, uint32_t, int, double *,
+                         hipStream_t);
+constexpr int kSampleTile = 256;
+}  // namespace tnmc
+
+using tnmc::InstDesc;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *what) {
+    return fail(TNMC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct tnmc_env {
+    int32_t batch = 0, precision = 0, chi_bucket = 0, max_tiles = 0;
+    std::vector<int32_t> L, chi;
+    std::vector<double> beta;
+    const float *J_h = nullptr, *J_v = nullptr;
+    std::vector<InstDesc> desc;
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0, tile_bytes = 0, desc_off = 0, sweeps_off = 0;
+};
+
+namespace {
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+size_t tsize_of(int prec) { return prec == TNMC_FP64 ? 8 : 4; }
+size_t ssize_of(int prec) {
+    switch (prec) {
+    case TNMC_FP64: return 8;
+    case TNMC_FP32: return 4;
+    default: return 2;
+    }
+}
+
+int chi_bucket_of(int chi) { return chi <= 16 ? 16 : (chi <= 32 ? 32 : 64); }
+
+struct Plan {
+    std::vector<InstDesc> desc;
+    size_t desc_off = 0, sweeps_off = 0, fixed = 0, tile_bytes = 0;
+    int chi_bucket = 16, chi_max = 2, L_max = 2;
+};
+
+int validate(const tnmc_problem *p, int precision, bool need_data) {
+    if (!p) return fail(TNMC_EINVAL, "problem is NULL");
+    if (p->batch < 1) return fail(TNMC_EINVAL, "batch must be >= 1");
+    if (!p->L || !p->chi || !p->beta) return fail(TNMC_EINVAL, "L, chi and beta must be non-NULL host arrays");
+    if (need_data && (!p->J_h || !p->J_v)) return fail(TNMC_EINVAL, "J_h and J_v must be non-NULL device arrays");
+    if (precision < TNMC_FP64 || precision > TNMC_MIXED_FP16) return fail(TNMC_EINVAL, "unknown precision");
+    for (int i = 0; i < p->batch; ++i) {
+        const int L = p->L[i], chi = p->chi[i];
+        const double b = p->beta[i];
+        if (L < 2 || L > TNMC_L_MAX)
+            return fail(TNMC_EINVAL, "instance " + std::to_string(i) + ": L must be in [2, " + std::to_string(TNMC_L_MAX) + "]");
+        if (chi < 2 || chi > TNMC_CHI_MAX)
+            return fail(TNMC_EINVAL, "instance " + std::to_string(i) + ": chi must be in [2, 64]");
+        if (!std::isfinite(b) || b < 0.0)
+            return fail(TNMC_EINVAL, "instance " + std::to_string(i) + ": beta must be finite and >= 0");
+        if (precision == TNMC_FP64 && chi > 32)
+            return fail(TNMC_ENOTSUP, "float64 path supports chi <= 32 (instance " + std::to_string(i) + ")");
+        if (p->off_h && p->off_h[i] < 0) return fail(TNMC_EINVAL, "negative J_h offset");
+        if (p->off_v && p->off_v[i] < 0) return fail(TNMC_EINVAL, "negative J_v offset");
+    }
+    return TNMC_OK;
+}
+
+// Workspace layout: [desc table][sweep counts][per instance: log-scales,
+// cache, build scratch, (float ping-pong)][sampler env tiles ...].
+int plan(const tnmc_problem *p, int precision, Plan &pl) {
+    const size_t ts = tsize_of(precision), ss = ssize_of(precision);
+    const bool pingpong = precision >= TNMC_MIXED_BF16;
+    const int B = p->batch;
+    pl.desc.assign(B, InstDesc{});
+    for (int i = 0; i < B; ++i) {
+        pl.chi_max = std::max(pl.chi_max, p->chi[i]);
+        pl.L_max = std::max(pl.L_max, p->L[i]);
+    }
+    pl.chi_bucket = chi_bucket_of(pl.chi_max);
+    size_t off = 0;
+    pl.desc_off = off;
+    off = align_up(off + sizeof(InstDesc) * B);
+    pl.sweeps_off = off;
+    off = align_up(off + sizeof(int64_t) * 4 * B);
+    int64_t oh = 0, ov = 0, wp = 0, sp = 0;
+    for (int i = 0; i < B; ++i) {
+        InstDesc &d = pl.desc[i];
+        const int L = p->L[i], chi = p->chi[i];
+        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.pad0 = 0;
+        d.beta = p->beta[i];
+        d.off_h = p->off_h ? p->off_h[i] : oh;
+        d.off_v = p->off_v ? p->off_v[i] : ov;
+        oh += (int64_t)L * (L - 1);
+        ov += (int64_t)(L - 1) * L;
+        d.word_prefix = wp;
+        d.site_prefix = sp;
+        wp += (int64_t)L * d.W;
+        sp += (int64_t)L * L;
+        d.lsc_off = off;
+        off = align_up(off + sizeof(double) * L);
+        d.cache_off = off;
+        off = align_up(off + (size_t)L * L * 2 * chi * chi * ss);
+        d.qscr_off = off;
+        off = align_up(off + (size_t)L * 2 * 2 * chi * chi * ts);
+        if (pingpong) {
+            d.prev_off = off;
+            off = align_up(off + (size_t)2 * L * 2 * chi * chi * ts);
+        } else {
+            d.prev_off = 0;
+        }
+    }
+    pl.fixed = off;
+    size_t tb = 0;
+    for (int i = 0; i < B; ++i) {
+        pl.desc[i].env_off = off + tb;
+        tb = align_up(tb + (size_t)tnmc::kSampleTile * p->L[i] * pl.chi_bucket * ts);
+    }
+    pl.tile_bytes = tb;
+    return TNMC_OK;
+}
+
+int check_lds(int precision, int chi_max, int L_max) {
+    const size_t need = tnmc::build_lds_bytes(chi_max, L_max, tsize_of(precision));
+    int dev = 0, lim = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    if (need > (size_t)lim)
+        return fail(TNMC_ENOTSUP, "build needs " + std::to_string(need) + " bytes of LDS per workgroup, device allows " + std::to_string(lim));
+    return TNMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tnmc_last_error(void) { return g_err.c_str(); }
+
+int tnmc_workspace_size(const tnmc_problem *p, int32_t precision, int32_t max_samples, size_t *bytes_out) {
+    int rc = validate(p, precision, false);
+    if (rc) return rc;
+    if (max_samples < 1) return fail(TNMC_EINVAL, "max_samples must be >= 1");
+    if (!bytes_out) return fail(TNMC_EINVAL, "bytes_out is NULL");
+    Plan pl;
+    plan(p, precision, pl);
+    const size_t tiles = (size_t)(max_samples + tnmc::kSampleTile - 1) / tnmc::kSampleTile;
+    *bytes_out = pl.fixed + tiles * pl.tile_bytes;
+    return TNMC_OK;
+}
+
+int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
+                   void *stream, tnmc_env **env_out, double *logz_out) {
+    int rc = validate(p, precision, true);
+    if (rc) return rc;
+    if (!env_out) return fail(TNMC_EINVAL, "env_out is NULL");
+    if (!workspace) return fail(TNMC_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(TNMC_EINVAL, "workspace must be 256-byte aligned");
+    Plan pl;
+    plan(p, precision, pl);
+    if (workspace_bytes < pl.fixed + pl.tile_bytes)
+        return fail(TNMC_ENOSPACE, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs at least " + std::to_string(pl.fixed + pl.tile_bytes));
+    rc = check_lds(precision, pl.chi_max, pl.L_max);
+    if (rc) return rc;
+    tnmc_env *env = new tnmc_env();
+    env->batch = p->batch;
+    env->precision = precision;
+    env->chi_bucket = pl.chi_bucket;
+    env->L.assign(p->L, p->L + p->batch);
+    env->chi.assign(p->chi, p->chi + p->batch);
+    env->beta.assign(p->beta, p->beta + p->batch);
+    env->J_h = p->J_h;
+    env->J_v = p->J_v;
+    env->desc = pl.desc;
+    env->ws = static_cast<unsigned char *>(workspace);
+    env->ws_bytes = workspace_bytes;
+    env->tile_bytes = pl.tile_bytes;
+    env->desc_off = pl.desc_off;
+    env->sweeps_off = pl.sweeps_off;
+    env->max_tiles = (int)((workspace_bytes - pl.fixed) / pl.tile_bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(env->ws + pl.desc_off, env->desc.data(), sizeof(InstDesc) * p->batch,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { delete env; return hip_fail(e, "descriptor upload"); }
+    const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
+    int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
+    const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
+    switch (precision) {
+    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    default: e = tnmc::launch_build<float, __half>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    }
+    if (e != hipSuccess) { delete env; return hip_fail(e, "build launch"); }
+    *env_out = env;
+    return TNMC_OK;
+}
+
+int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed, uint64_t sample_offset,
+                const uint64_t *forced_spins, const tnmc_mlp *mlp, uint64_t *spins_out,
+                double *logq_out, float *logits_out, void *stream) {
+    if (!env) return fail(TNMC_EINVAL, "env is NULL");
+    if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
+    if (!spins_out || !logq_out) return fail(TNMC_EINVAL, "spins_out and logq_out must be non-NULL");
+    const int tiles = (n_samples + tnmc::kSampleTile - 1) / tnmc::kSampleTile;
+    if (tiles > env->max_tiles)
+        return fail(TNMC_ENOSPACE, "workspace sized for " + std::to_string(env->max_tiles * tnmc::kSampleTile) + " samples per call");
+    if (mlp) return fail(TNMC_ENOTSUP, "learned correction not available in this build");
+    tnmc::MlpArgs ma{};
+    const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + env->desc_off);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    switch (env->precision) {
+    case TNMC_FP64: e = tnmc::launch_sample<double, double>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
+    case TNMC_FP32: e = tnmc::launch_sample<float, float>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
+    case TNMC_MIXED_BF16: e = tnmc::launch_sample<float, __hip_bfloat16>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
+    default: e = tnmc::launch_sample<float, __half>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "sample launch");
+    return TNMC_OK;
+}
+
+int tnmc_energy(const tnmc_env *env, int32_t n_samples, const uint64_t *spins, double *E_out, void *stream) {
+    if (!env) return fail(TNMC_EINVAL, "env is NULL");
+    if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
+    if (!spins || !E_out) return fail(TNMC_EINVAL, "spins and E_out must be non-NULL");
+    const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + env->desc_off);
+    hipError_t e = tnmc::launch_energy(dd, env->batch, n_samples, spins, env->J_h, env->J_v, E_out,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    return TNMC_OK;
+}
+
+int tnmc_accept(int32_t batch, int32_t n_samples, const double *logq, const double *E, const double *beta,
+                tnmc_chain *chain, uint64_t seed, uint64_t step_offset, uint8_t *accepted_out,
+                int64_t *state_out, void *stream) {
+    if (batch < 1 || n_samples < 1) return fail(TNMC_EINVAL, "batch and n_samples must be >= 1");
+    if (!logq || !E || !beta || !chain || !accepted_out) return fail(TNMC_EINVAL, "NULL array argument");
+    hipError_t e = tnmc::launch_accept(batch, n_samples, logq, E, beta, chain, seed, step_offset, accepted_out,
+                                       state_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "accept launch");
+    return TNMC_OK;
+}
+
+void tnmc_free_env(tnmc_env *env) { delete env; }
+
+int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1, uint32_t c2, uint32_t stream_id,
+                        int32_t n, double *out, void *stream) {
+    if (n < 1 || !c0 || !out) return fail(TNMC_EINVAL, "bad philox arguments");
+    hipError_t e = tnmc::launch_philox(seed, c0, c1, c2, stream_id, n, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "philox launch");
+    return TNMC_OK;
+}
+
+const int64_t *tnmc_env_stats(const tnmc_env *env) {
+    if (!env) return nullptr;
+    return reinterpret_cast<const int64_t *>(env->ws + env->sweeps_off);
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: float64 log q and ln Z within 1e-10 * max(1, |value|) of the
+oracle; float32 within 2e-4 * max(1, |value|) (accumulation over ~L^2
+float32 contractions); energies, Philox draws and accept decisions
+bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import bmps, exact, ising, mis, philox, sampler
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 2e-4}
+
+
+def rel_err(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(1.0, np.abs(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def G(tnmc):
+    import tnmc_gpu
+    return tnmc_gpu
+
+
+def test_philox_bit_exact(G, tnmc):
+    import torch
+    G.say("philox: 1<<20 counters")
+    c0 = np.arange(1 << 20, dtype=np.uint32) * np.uint32(2654435761)
+    t0 = torch.as_tensor(c0.view(np.int32)).cuda()
+    out = torch.zeros(c0.size, dtype=torch.float64, device="cuda")
+    for seed, c1, c2, st in [(0, 0, 0, 0), (0xDEADBEEF12345678, 7, 3, 1), (5, 123456, 99, 0)]:
+        tnmc.tnmc_philox_uniform(seed, t0, c1, c2, st, out)
+        torch.cuda.synchronize()
+        want = philox.uniform(seed, c0.astype(np.uint64), c1, c2, st)
+        assert np.array_equal(out.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("fam", ["pmj", "gauss"])
+def test_energy_bit_exact(G, tnmc, fam):
+    Ls = [5, 64, 65, 130]
+    Js = [workloads.instance(L, fam, 40, i) for i, L in enumerate(Ls)]
+    G.say(f"energy {fam} L={Ls}")
+    run = G.Run(Js, 4, 1.0, tnmc.FP32, max_samples=8)
+    spins = [workloads.random_spins(7, L, 100 + L) for L in Ls]
+    E = run.energy(spins)
+    for i, (jh, jv) in enumerate(Js):
+        want = ising.energy(spins[i], jh, jv)
+        assert np.array_equal(E[i], want)
+        assert np.array_equal(run.energy([-s for s in spins])[i], want)
+
+
+def test_accept_bit_exact_on_identical_inputs(G, tnmc):
+    rng = np.random.default_rng(5)
+    B, n = 37, 300
+    lq = rng.normal(-50, 3, (B, n))
+    E = np.round(rng.normal(-100, 4, (B, n)))
+    beta = rng.uniform(0.5, 2.0, B)
+    G.say("accept: 37 chains x 300 proposals, split 120 + 180")
+    acc, st, chain = G.gpu_accept(lq[:, :120], E[:, :120], beta, 77, 0)
+    acc2, st2, chain = G.gpu_accept(lq[:, 120:], E[:, 120:], beta, 77, 120, chain)
+    acc = np.concatenate([acc, acc2], 1)
+    st = np.concatenate([st, st2], 1)
+    states = tnmc.chain_state(chain.cpu().numpy())
+    for i in range(B):
+        ch = mis.Chain()
+        a, s = mis.accept(lq[i], E[i], beta[i], ch, 77, i, 0)
+        assert np.array_equal(a, acc[i]) and np.array_equal(s, st[i])
+        assert states[i]["n_acc"] == ch.n_acc and states[i]["n_trials"] == ch.n_trials
+        assert states[i]["cur_index"] == ch.cur_index and states[i]["cur_logq"] == ch.cur_logq
+
+
+def _oracle_build(Js, chi, beta):
+    return [bmps.build_cache(beta, jh, jv, chi) for jh, jv in Js]
+
+
+CASES = [
+    # (name, L list, family, chi, beta, precision)
+    ("3x3 exact", [3, 3], "pmj", 2, 1.0, 0),
+    ("4x4 exact", [4, 4], "gauss", 4, 1.5, 0),
+    ("C1 8x8 chi16", [8] * 4, "pmj", 16, 1.0, 0),
+    ("12x12 chi4 trunc", [12, 12], "gauss", 4, 1.0, 0),
+    ("16x16 chi32", [16, 16], "gauss", 32, 1.0, 0),
+    ("uneven L", [2, 5, 9, 17], "pmj", 8, 0.7, 0),
+    ("16x16 chi8 fp32", [16, 16], "gauss", 8, 1.0, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_logz_and_teacher_forced_logq(G, tnmc, case):
+    name, Ls, fam, chi, beta, prec = case
+    Js = [workloads.instance(L, fam, 41, i) for i, L in enumerate(Ls)]
+    G.say(f"build+score {name}: L={Ls} chi={chi} beta={beta} prec={prec}")
+    run = G.Run(Js, chi, beta, prec, max_samples=300)
+    orc = _oracle_build(Js, chi, beta)
+    tol = TOL[prec]
+    lz = run.logz
+    for i in range(len(Js)):
+        assert rel_err(lz[i], orc[i][2]) < tol, (i, lz[i], orc[i][2])
+        if Ls[i] ** 2 <= 16 and chi >= 2 ** (Ls[i] // 2):
+            assert rel_err(lz[i], exact.brute_logZ(*Js[i], beta)) < tol
+    # Score configurations the method itself proposes (oracle draws): at
+    # truncated chi a uniformly random configuration has conditionals that
+    # are differences of nearly cancelling terms, where any two correct
+    # implementations differ by far more than rounding.
+    k, n = 12, 300          # 300 = two sample tiles, the second ragged
+    draws = [sampler.sample(orc[i][0], beta, Js[i][1], k, seed=99, instance=i)
+             for i in range(len(Js))]
+    forced = [np.tile(2 * d[0] - 1, (n // k + 1, 1, 1))[:n] for d in draws]
+    _, lq, lg = run.sample(n, forced=forced, logits=True)
+    for i in range(len(Js)):
+        olq, olg = draws[i][1], draws[i][2]
+        want = np.tile(olq, n // k + 1)[:n]
+        assert np.max(rel_err(lq[i], want)) < tol, (i, np.max(np.abs(lq[i] - want)))
+        fin = np.isfinite(olg)
+        assert np.max(np.abs(lg[i][:k][fin] - olg[fin])) < (1e-4 if prec == 0 else 2e-2)
+    # the Z2 partner scores the same
+    _, lq_m, _ = run.sample(k, forced=[-f[:k] for f in forced])
+    assert np.max(rel_err(lq_m, lq[:, :k])) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_free_sampling_matches_oracle_draws(G, tnmc, prec):
+    L, chi, beta = 10, 4, 1.0
+    Js = [workloads.instance(L, "gauss", 42, i) for i in range(3)]
+    G.say(f"free sampling L={L} chi={chi} prec={prec}")
+    run = G.Run(Js, chi, beta, prec, max_samples=64)
+    sp, lq, _ = run.sample(64, seed=1234, offset=1000)
+    mism = 0
+    for i, (jh, jv) in enumerate(Js):
+        cache, _, _ = bmps.build_cache(beta, jh, jv, chi)
+        bits, olq, _ = sampler.sample(cache, beta, jv, 64, seed=1234, instance=i, sample_offset=1000)
+        same = np.all(sp[i] == 2 * bits - 1, axis=(1, 2))
+        mism += int((~same).sum())
+        assert np.max(rel_err(lq[i][same], olq[same])) < TOL[prec]
+    # a draw flips only when u falls within the logit error of p: rare
+    assert mism <= (0 if prec == 0 else 3)
+
+
+def test_c1_exact_regime_accepts_everything(G, tnmc):
+    """8x8 +-J, beta 1, chi 16 (exact), 4 disorders x 64 samples, one pass."""
+    L, chi, beta, B, n = 8, 16, 1.0, 4, 64
+    Js = [workloads.instance(L, "pmj", 1, i) for i in range(B)]
+    G.say("C1 end to end")
+    run = G.Run(Js, chi, beta, 0, max_samples=n)
+    sp, lq, _ = run.sample(n, seed=0x5A5A0001)
+    E = run.energy(sp)
+    lz = run.logz
+    for i, (jh, jv) in enumerate(Js):
+        _, _, tz = exact.transfer_vectors(jh, jv, beta)
+        assert rel_err(lz[i], tz) < 1e-10
+        assert np.max(rel_err(lq[i], -beta * E[i] - tz)) < 1e-10
+    acc, _, chain = G.gpu_accept(lq, E, np.full(B, beta), 0x5A5A0001, 0)
+    assert acc.all()
+    st = tnmc.chain_state(chain.cpu().numpy())
+    assert all(s["n_acc"] == n - 1 and s["n_trials"] == n - 1 for s in st)
