@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the batched TNMC hot path on one MI355X.
+
+One step = the whole path over one batch of synthetic disorders: boundary-MPS
+cache build (tnmc_build_env), sampling (tnmc_sample), exact energies
+(tnmc_energy) and the Metropolis independence step (tnmc_accept), all on one
+stream with the couplings already resident in HBM.  Workload (default): the
+mixed-precision configuration -- 256 x 256 open-boundary +-J Edwards-Anderson
+lattices, beta = 1, chi = 32, 256 disorders x 256 samples; the same inputs are
+also run through the plain float32 path.  The Markov chains continue across
+steps; accepted samples are accepted Metropolis trials.
+
+Prints one JSON line (rank 0) with the headline value (mixed form), the plain
+float32 comparison, a roofline entry for the dominant kernel (the cache
+build) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "accepted samples/s at L=256 chi=32 + acceptance rate, learned/mixed vs plain"
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}          # MI355X vector peaks, flop/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_flops_model(L, chi, B):
+    """Algorithmic flops of one cache build: per site of every row above the
+    bottom one, 32 chi^2 + (101 + 48 S) chi^3 with S = 8 Jacobi sweeps (the
+    dense boundary-MPS cost model: MPO apply, QR sweep, SVD sweep)."""
+    per_site = 32 * chi ** 2 + (101 + 48 * 8) * chi ** 3
+    return B * (L - 1) * L * per_site
+
+
+def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed):
+    problem = T.Problem(jh, jv, [L] * B, chi, beta)
+    nbytes = T.tnmc_workspace_size(problem, prec, N)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    words = N * problem.spin_words_per_sample()
+    spins = torch.empty(words, dtype=torch.int64, device="cuda")
+    logq = torch.empty((B, N), dtype=torch.float64, device="cuda")
+    E = torch.empty((B, N), dtype=torch.float64, device="cuda")
+    acc = torch.empty((B, N), dtype=torch.uint8, device="cuda")
+    chain = torch.zeros(B * T.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
+    beta_t = torch.full((B,), float(beta), dtype=torch.float64, device="cuda")
+    logz = torch.empty(B, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    envs = []
+
+    def step(k, marks=None):
+        if marks: marks[0].record(stream)
+        env = T.tnmc_build_env(problem, prec, ws, logz)
+        if marks: marks[1].record(stream)
+        T.tnmc_sample(env, N, seed, spins, logq, sample_offset=k * N)
+        if marks: marks[2].record(stream)
+        T.tnmc_energy(env, N, spins, E)
+        if marks: marks[3].record(stream)
+        T.tnmc_accept(logq, E, beta_t, chain, seed, k * N, acc)
+        if marks: marks[4].record(stream)
+        envs.append(env)
+
+    for w in range(warmup):
+        step(10_000 + w)
+        torch.cuda.synchronize()
+        log(f"  warmup step {w} done")
+    chain.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k, ev[k])
+        torch.cuda.synchronize()
+        log(f"  step {k}: build {ev[k][0].elapsed_time(ev[k][1]):.0f} ms, "
+            f"sample {ev[k][1].elapsed_time(ev[k][2]):.0f} ms")
+    wall = time.perf_counter() - t0
+    st = T.chain_state(chain.cpu().numpy())
+    n_acc = sum(s["n_acc"] for s in st)
+    n_tr = sum(s["n_trials"] for s in st)
+    phase = [sum(ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)) / steps for i in range(4)]
+    stats = T.tnmc_env_stats(envs[-1])
+    out = dict(value=n_acc / wall, acceptance=n_acc / max(1, n_tr), accepted=n_acc, trials=n_tr,
+               wall_s=wall, ms_per_step=1e3 * wall / steps,
+               build_ms=phase[0], sample_ms=phase[1], energy_ms=phase[2], accept_ms=phase[3],
+               jacobi_sweeps_per_site=float(stats[:, 0].mean()) / ((L - 1) * L),
+               logz_mean=float(logz.mean().item()))
+    del envs, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(L, chi, beta, N, acceptance, jh, jv, build_rows=36, sample_rows=3, n_sample=8):
+    """The oracle, timed on a bounded sample of one instance of the workload:
+    `build_rows` bulk rows of the cache build (after the bonds have reached
+    chi) and `sample_rows` rows of sampling for `n_sample` samples, scaled to
+    a whole instance (L-1 rows built, N samples of L rows)."""
+    import numpy as np
+    from oracle import bmps, sampler
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    jh = jh.astype(np.float64)
+    jv = jv.astype(np.float64)
+    mps, _ = bmps.bottom_row_mps(beta, jh)
+    row = L - 2
+    for _ in range(int(math.log2(chi)) + 2):                 # bonds grow to chi
+        mps = bmps.multiply(bmps.row_mpo(beta, jh, jv, row), mps)
+        _, mps = bmps.compress(mps, chi)
+        row -= 1
+    t0 = time.perf_counter()
+    for _ in range(build_rows):
+        mps = bmps.multiply(bmps.row_mpo(beta, jh, jv, row), mps)
+        _, mps = bmps.compress(mps, chi)
+        row -= 1
+    t_row = (time.perf_counter() - t0) / build_rows
+    rng = np.random.default_rng(0)
+    u = rng.integers(0, 2, (n_sample, L))
+    t0 = time.perf_counter()
+    for _ in range(sample_rows):
+        sampler.sample_row(mps, beta, jv[row], u, n_sample, uniforms=rng.random((n_sample, L)))
+    t_srow = (time.perf_counter() - t0) / (sample_rows * n_sample)
+    per_instance = (L - 1) * t_row + N * L * t_srow
+    return {"value": acceptance * N / per_instance, "unit": "accepted samples/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"one {L}x{L} chi={chi} instance: {build_rows} bulk rows of the float64 cache "
+                       f"build ({t_row:.3f} s/row) and {sample_rows} rows x {n_sample} samples of "
+                       f"sampling ({t_srow * 1e3:.2f} ms per sample-row), scaled to {L - 1} rows and "
+                       f"{N} samples; acceptance taken from the float32 GPU run")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=256)
+    ap.add_argument("--chi", type=int, default=32)
+    ap.add_argument("--disorders", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--beta", type=float, default=1.0)
+    ap.add_argument("--mixed", choices=["bf16", "fp16"], default="bf16")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain float32 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of this many GiB three times "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the instances are independent and this build runs "
+              "on a single MI355X; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * (1 << 30))
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {n} bytes")
+        return
+    import paper_2509_19006_amd as T
+    import workloads
+    T.load()
+
+    L, chi, B, N, beta = args.L, args.chi, args.disorders, args.samples, args.beta
+    log(f"workload: {B} +-J disorders of {L}x{L}, beta={beta}, chi={chi}, {N} samples each")
+    jh_np, jv_np = workloads.batch(L, B, "pmj", 3)
+    jh = torch.as_tensor(jh_np).cuda()
+    jv = torch.as_tensor(jv_np).cuda()
+    seed = 0x5A5A0003
+
+    mixed_prec = T.MIXED_BF16 if args.mixed == "bf16" else T.MIXED_FP16
+    log(f"mixed form ({args.mixed} cache, float32 build):")
+    mixed = run_form(T, torch, mixed_prec, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+    plain = None
+    if not args.no_plain:
+        log("plain float32 form:")
+        plain = run_form(T, torch, T.FP32, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+
+    flops = build_flops_model(L, chi, B)
+    achieved = flops / (mixed["build_ms"] * 1e-3)
+    roof = {"bound": "alu", "kernel": "k_build (cache build, float32 arithmetic)",
+            "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK["fp32"], "traffic": None,
+            "flops_per_launch": flops,
+            "per_unit": "32 chi^2 + 485 chi^3 flop per site-row (dense cost model, 8 sweeps)",
+            "units_per_launch": B * (L - 1) * L}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        acc_ref = (plain or mixed)["acceptance"]
+        cpu = cpu_baseline(L, chi, beta, N, acc_ref, jh_np[0], jv_np[0])
+
+    line = {
+        "metric": METRIC, "value": mixed["value"], "unit": "accepted samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"mixed-precision TNMC: {L}x{L} open +-J EA lattices, beta={beta}, "
+                                f"chi={chi}, {B} disorders x {N} samples, {args.mixed} cache, float32 "
+                                "build, float64 log-weights and accept"),
+                   "L": L, "chi": chi, "disorders": B, "samples": N, "beta": beta,
+                   "form": f"mixed-{args.mixed}"},
+        "acceptance": mixed["acceptance"],
+        "mixed": mixed, "plain_fp32": plain,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,12 +100,16 @@ def multiply(mpo, mps):
     return out
 
 
-def compress(mps, chi: int):
+def compress(mps, chi: int, diag=None):
     """QR sweep left->right, then truncating SVD sweep right->left.
 
     Returns (log of the norms taken out, new list of sites).  Bond c|c+1 ends
     with dimension min(chi, rank bound); the singular values kept are the
-    largest ones, with no cutoff.
+    largest ones, with no cutoff.  If `diag` is a dict, diag["cond"] is raised
+    to the largest sigma_k / (sigma_k - sigma_{k+1}) over the cuts that
+    discard something (sigma_k above 1e-13 sigma_1): the factor by which
+    rounding is amplified in the truncated state when the cut falls inside a
+    near-degenerate pair (infinite for an exact tie).
     """
     mps = [t.copy() for t in mps]
     L = len(mps)
@@ -123,6 +127,9 @@ def compress(mps, chi: int):
         Dl, d, Dr = mps[c].shape
         U, S, Vt = np.linalg.svd(mps[c].reshape(Dl, d * Dr), full_matrices=False)
         k = min(chi, S.shape[0])
+        if diag is not None and k < S.shape[0] and S[k - 1] > 1e-13 * S[0]:
+            gap = S[k - 1] - S[k]
+            diag["cond"] = max(diag.get("cond", 0.0), S[k - 1] / gap if gap > 0 else math.inf)
         U, S, Vt = U[:, :k], S[:k], Vt[:k]
         nrm = float(np.linalg.norm(S))
         logn += math.log(nrm)
@@ -133,12 +140,13 @@ def compress(mps, chi: int):
     return logn, mps
 
 
-def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int):
+def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int, diag=None):
     """The full cache for one instance.
 
     Returns (cache, logscale, logZ) where cache[r] is the list of row r's
     site tensors (shapes (Dl, 2, Dr), normalised), logscale[r] the log of the
     norms taken out when row r was formed, and logZ the TN estimate of ln Z.
+    `diag` (optional dict) collects the truncation conditioning, see compress.
     """
     J_h = np.asarray(J_h, dtype=np.float64)
     J_v = np.asarray(J_v, dtype=np.float64)
@@ -149,7 +157,7 @@ def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int):
     cache[L - 1] = mps
     for row in range(L - 2, -1, -1):
         mps = multiply(row_mpo(beta, J_h, J_v, row), mps)
-        logscale[row], mps = compress(mps, chi)
+        logscale[row], mps = compress(mps, chi, diag)
         cache[row] = mps
     return cache, logscale, float(logscale.sum() + log_total(cache[0]))
 

@@ -100,11 +100,10 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
     return TNMC_OK;
 }
 
-// Workspace layout: [desc table][sweep counts][per instance: log-scales,
-// cache, build scratch, (float ping-pong)][sampler env tiles ...].
+// Workspace layout: [desc table][build stats][per instance: log-scales,
+// cache, build scratch, previous-row ping-pong][sampler env tiles ...].
 int plan(const tnmc_problem *p, int precision, Plan &pl) {
     const size_t ts = tsize_of(precision), ss = ssize_of(precision);
-    const bool pingpong = precision >= TNMC_MIXED_BF16;
     const int B = p->batch;
     pl.desc.assign(B, InstDesc{});
     for (int i = 0; i < B; ++i) {
@@ -137,12 +136,8 @@ int plan(const tnmc_problem *p, int precision, Plan &pl) {
         off = align_up(off + (size_t)L * L * 2 * chi * chi * ss);
         d.qscr_off = off;
         off = align_up(off + (size_t)L * 2 * 2 * chi * chi * ts);
-        if (pingpong) {
-            d.prev_off = off;
-            off = align_up(off + (size_t)2 * L * 2 * chi * chi * ts);
-        } else {
-            d.prev_off = 0;
-        }
+        d.prev_off = off;      // previous row in the parity basis (build arithmetic type)
+        off = align_up(off + (size_t)2 * L * 2 * chi * chi * ts);
     }
     pl.fixed = off;
     size_t tb = 0;

@@ -2,29 +2,42 @@
 // section 3.2): starting from the bottom row, apply each row's transfer MPO
 // to the boundary MPS and truncate back to bond dimension chi.
 //
+// Spin-flip (Z2) symmetric formulation.  With no field every Boltzmann matrix
+// (Eq. 7) is symmetric under flipping both spins, so in the basis
+// h_0 = (1,1)/sqrt2 (even), h_1 = (1,-1)/sqrt2 (odd) it is diagonal with
+// eigenvalues lam = (a+b, a-b), and every copy tensor (Eq. 8) becomes a
+// parity constraint (legs' parities sum to even).  In that basis every bond
+// of the boundary MPS splits into an even and an odd sector (stored as one
+// index: even entries first), site tensors are parity conserving, and the
+// matrices the compression decomposes are block diagonal.  The truncated
+// state is the one the plain SVD sweep produces (exactly, in exact
+// arithmetic): keeping the chi largest singular values of a block-diagonal
+// matrix means keeping the largest of both blocks together.  The even/odd
+// pairs of nearly equal singular values that a spin-flip symmetric state
+// has never meet inside one Jacobi problem, which is what makes the
+// one-sided Jacobi converge in few sweeps.
+//
 // One workgroup (256 threads, 4 waves) owns one instance and walks its rows
 // bottom to top.  Per row:
-//   * apply   -- the MPO of a row is built from copy tensors (Eq. 8) and
-//                Boltzmann matrices (Eq. 7).  Its copy-tensor structure means
-//                that site c of MPO x MPS, for physical spin s, is
-//                Bh(c-1)[l,s] * delta(t,s) * C_s with
-//                C_s = sum_n Bv(c)[s,n] A_old[:,n,:]
-//                (the new right bond carries the spin t = s).  The tensor is
-//                never formed densely.
-//   * QR sweep, left to right -- because the new right bond carries s, the
-//                matrix R * A'_c splits into two blocks M_s (one per s), each
-//                (2 m_prev) x D_old; each gets its own Householder QR.
-//   * SVD sweep, right to left -- center matrix T = [Q_0 X_0, Q_1 X_1]
-//                (K x 2k); one-sided (Hestenes) Jacobi with a round-robin
-//                pair order; keep the chi largest singular values, the right
-//                factor V^T becomes the site, U*S moves to the left.
-// All norms removed along the way go to a float64 log-scale per row, so that
-// ln Z = sum_r logscale[r] + ln(row-0 MPS with every spin summed).
+//   * apply   -- site c of MPO x MPS is A'[(a,l),s,(b,t)] =
+//                lam_h(c-1)[l] lam_v(c)[n] A_old[a,n,b], n = l^s^t; never
+//                formed, folded into the next step;
+//   * QR sweep, left to right -- R * A'_c splits into two parity blocks
+//                M^p = [Rh^p C ; Rh^(1-p) C] with C[a,b] = lam_v[pa^pb] *
+//                A_old[a, pa^pb, b] and Rh^q = R^q scaled column-wise by
+//                lam_h[q ^ pa]; each block gets a Householder QR;
+//   * SVD sweep, right to left -- center T^p = [Q^p_0 X^p, Q^(1-p)_1 X^(1-p)]
+//                for p = 0, 1; one-sided (Hestenes) Jacobi on both blocks at
+//                once (round-robin pair order); keep the chi largest singular
+//                values over both; V^T becomes the site, U*S moves left.
+// The cache is written in the spin basis, A[x] = (A~[even] + (-1)^x A~[odd])
+// / sqrt2, which is what the sampler contracts.  All norms removed along the
+// way go to a float64 log-scale per row, so that ln Z = sum_r logscale[r] +
+// (L/2) ln 2 + ln(row-0 MPS contracted on its even physical component).
 //
 // Template T is the arithmetic type (double or float); S the cache storage
-// type (double, float, bfloat16 or half).  When S != T the previous row is
-// also kept in a float ping-pong buffer so the build never reads rounded
-// values back.
+// type (double, float, bfloat16 or half).  The previous row is kept in T in a
+// parity-basis ping-pong buffer, so the build never reads rounded values.
 #include <type_traits>
 
 #include "device.hpp"
@@ -34,13 +47,27 @@ namespace tnmc {
 constexpr int NT = 256;
 constexpr int MAX_SWEEPS = 40;
 
-template <typename T> __device__ __forceinline__ T shfl_xor_t(T v, int m, int w) {
-    return __shfl_xor(v, m, w);
+// Cross-lane moves inside 16-lane rows use DPP (no trip through the LDS
+// permute unit); wider steps fall back to __shfl_xor.
+template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over groups of G consecutive lanes (G a power of two <= 64).
+// Sum over aligned groups of G consecutive lanes (G a power of two <= 64);
+// every lane of a group gets the group's sum.
 template <typename T> __device__ __forceinline__ T group_sum(T v, int G) {
-    for (int m = G >> 1; m > 0; m >>= 1) v += shfl_xor_t(v, m, 64);
+    if (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror: partner in the other quad
+    if (G >= 16) v += dpp_move<0x140>(v);  // row_mirror: partner in the other half-row
+    if (G >= 32) v += __shfl_xor(v, 16, 64);
+    if (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -52,7 +79,7 @@ __device__ __forceinline__ int pow2_floor(int x) {
 
 // Workgroup sum of one double (all threads get the result).
 __device__ double block_sum(double v, double *red) {
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    v = group_sum(v, 64);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -82,43 +109,51 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
     return y * (1.5f - 0.5f * x * y * y);
 }
 
-// One-sided (Hestenes) Jacobi on the n columns (length K) of Tm,
-// accumulating the rotations in Wm (n x n); both column-major with leading
-// dimension ld.  cn2[n] holds squared column norms: recomputed at the start
-// of every sweep and carried through each rotation exactly
-// (a' = a - t*g, b' = b + t*g), so a pair needs a single reduction.  Pairs
-// whose smaller column is below sqrt(n)*eps*||T||_F are left alone: such
-// columns are rounding noise and a relative orthogonality test on them never
-// settles.  Returns the number of sweeps.
+// One-sided (Hestenes) Jacobi on two independent blocks at once.  Block p
+// has n columns (length K[p]) starting at Tm + p*bs, rotations accumulated
+// in Wm + p*bs (n x n); column-major with leading dimension ld.  cn2[p*n+j]
+// holds squared column norms, recomputed every sweep and carried through
+// each rotation exactly (a' = a - t*g, b' = b + t*g), so a pair needs one
+// reduction.  Pairs whose smaller column is below sqrt(n)*eps*||T_p||_F are
+// left alone: such columns are rounding noise and a relative orthogonality
+// test on them never settles.  Returns the number of sweeps.
 template <typename T>
-__device__ int jacobi(T *Tm, T *Wm, int ld, int K, int n, T *cn2, int *flag) {
+__device__ int jacobi2(T *Tm, T *Wm, int ld, int bs, int K0, int K1, int n, T *cn2, T *small,
+                       int *flag) {
     const int tid = threadIdx.x;
-    const int npairs = n >> 1;
-    int G = pow2_floor(NT / npairs);
+    const int hp = n >> 1;                       // pairs per block per round
+    int G = pow2_floor(NT / (2 * hp));
     if (G > 64) G = 64;
     const int g = tid / G, lane = tid % G;
-    const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
-    T small = 0;
+    const int blk = g / hp, gg = g % hp;
+    const int K = blk == 0 ? K0 : K1;
+    const T tol = (T)2 * Eps<T>::v * sqrt((T)(K0 > K1 ? K0 : K1));
     int sweeps = 0;
     for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
-        for (int col = tid; col < n; col += NT) {
+        for (int e = tid; e < 2 * n; e += NT) {
+            const int b = e / n, col = e % n, kb = b == 0 ? K0 : K1;
+            const T *cp = Tm + b * bs + col * ld;
             T s2 = 0;
-            for (int r = 0; r < K; ++r) { const T v = Tm[col * ld + r]; s2 += v * v; }
-            cn2[col] = s2;
+            for (int r = 0; r < kb; ++r) s2 += cp[r] * cp[r];
+            cn2[e] = s2;
         }
         if (tid == 0) *flag = 0;
         __syncthreads();
         if (sw == 0) {
-            T fro = 0;
-            for (int col = 0; col < n; ++col) fro += cn2[col];
-            small = fro * Eps<T>::v * Eps<T>::v * (T)n;
+            if (tid < 2) {
+                T fro = 0;
+                for (int col = 0; col < n; ++col) fro += cn2[tid * n + col];
+                small[tid] = fro * Eps<T>::v * Eps<T>::v * (T)n;
+            }
+            __syncthreads();
         }
         for (int t = 0; t < n - 1; ++t) {
-            if (g < npairs) {
-                const int i = seat(g, t, n), j = seat(n - 1 - g, t, n);
-                const T a = cn2[i], b = cn2[j];
-                if (a > small && b > small) {
-                    T *ci = Tm + i * ld, *cj = Tm + j * ld;
+            if (blk < 2 && K > 0) {
+                const int i = seat(gg, t, n), j = seat(n - 1 - gg, t, n);
+                T *cn = cn2 + blk * n;
+                const T a = cn[i], b = cn[j], sm = small[blk];
+                if (a > sm && b > sm) {
+                    T *ci = Tm + blk * bs + i * ld, *cj = Tm + blk * bs + j * ld;
                     T c = 0;
                     for (int r = lane; r < K; r += G) c += ci[r] * cj[r];
                     c = group_sum(c, G);
@@ -133,15 +168,15 @@ __device__ int jacobi(T *Tm, T *Wm, int ld, int K, int n, T *cn2, int *flag) {
                             ci[r] = cs * x - sn * y;
                             cj[r] = sn * x + cs * y;
                         }
-                        T *wi = Wm + i * ld, *wj = Wm + j * ld;
+                        T *wi = Wm + blk * bs + i * ld, *wj = Wm + blk * bs + j * ld;
                         for (int r = lane; r < n; r += G) {
                             const T x = wi[r], y = wj[r];
                             wi[r] = cs * x - sn * y;
                             wj[r] = sn * x + cs * y;
                         }
                         if (lane == 0) {
-                            cn2[i] = a - tt * c;
-                            cn2[j] = b + tt * c;
+                            cn[i] = a - tt * c;
+                            cn[j] = b + tt * c;
                             *flag = 1;
                         }
                     }
@@ -157,147 +192,173 @@ __device__ int jacobi(T *Tm, T *Wm, int ld, int K, int n, T *cn2, int *flag) {
     return sweeps;
 }
 
+// Eigenvalues (even, odd) of the normalised Boltzmann matrix of one bond:
+// entries exp(beta*J*sx*sy - beta*|J|) are (1, x) or (x, 1) with
+// x = exp(-2 beta |J|), so lam = (1 + x, +-(1 - x)), sign of J.
+__device__ __forceinline__ void lam_of(double beta, float J, double &l0, double &l1) {
+    const double a = 2.0 * beta * fabs((double)J);
+    l0 = 1.0 + exp(-a);
+    const double d = -expm1(-a);
+    l1 = (J >= 0.0f) ? d : -d;
+}
+
 template <typename T, typename S>
 __global__ void __launch_bounds__(NT)
 k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
         const float *__restrict__ Jh_all, const float *__restrict__ Jv_all,
         double *__restrict__ logz_out, int64_t *__restrict__ stats_out) {
-    constexpr bool kPingPong = !std::is_same<T, S>::value;
     const int inst = blockIdx.x;
     const InstDesc d = desc[inst];
     const int L = d.L, chi = d.chi, tid = threadIdx.x;
     const double beta = d.beta;
+    const double LN2 = 0.69314718055994530942;
+    const T RS2 = (T)0.70710678118654752440;
     const float *jh = Jh_all + d.off_h;                  // [L][L-1]
     const float *jv = Jv_all + d.off_v;                  // [L-1][L]
-    S *cache = reinterpret_cast<S *>(ws + d.cache_off);  // [L][L][2][chi][chi]
+    S *cache = reinterpret_cast<S *>(ws + d.cache_off);  // [L][L][2][chi][chi], spin basis
     T *qscr = reinterpret_cast<T *>(ws + d.qscr_off);    // [L][2][2chi][chi]
-    T *prev = kPingPong ? reinterpret_cast<T *>(ws + d.prev_off) : nullptr;  // [2][L][2][chi][chi]
+    T *prev = reinterpret_cast<T *>(ws + d.prev_off);    // [2][L][2][chi][chi], parity basis
     double *lsc = reinterpret_cast<double *>(ws + d.lsc_off);
-    const size_t site_sz = (size_t)2 * chi * chi;
+    const int cc2 = chi * chi;
+    const size_t site_sz = (size_t)2 * cc2;
     const size_t row_sz = (size_t)L * site_sz;
     const int ldm = chi + 1;          // leading dim of M blocks
-    const int ldt = 2 * chi + 1;      // leading dim of Tm / Wm (column-major)
+    const int ldt = chi + 1;          // leading dim of Tm / Wm blocks (column-major)
+    const int bst = (chi + 1) * ldt;  // one Tm / Wm block
 
-    // ---- shared memory layout -------------------------------------------
+    // ---- shared memory layout (see build_lds_bytes) ----------------------
     extern __shared__ __align__(16) unsigned char smem[];
-    T *regA = reinterpret_cast<T *>(smem);                      // 4 chi^2
-    T *regB = regA + 4 * chi * chi;                             // 2*2chi*(chi+1)
-    T *Tm = regA;                                               // SVD phase: 2chi x ldt
-    T *Wm = regA + 2 * chi * ldt;                               //            2chi x ldt
-    T *tail = regA + (size_t)4 * chi * ldt;                     // >= 8chi^2+4chi
-    T *tau = tail;                                              // [2][chi]
-    T *nrm = tau + 2 * chi;                                     // [2chi]
-    double *red = reinterpret_cast<double *>(nrm + 2 * chi);    // [NT/64]
-    double *uvec = red + NT / 64;                               // [2][64] logZ vector
-    double *scal = uvec + 128;                                  // [4]
-    int *perm = reinterpret_cast<int *>(scal + 4);              // [2chi]
-    int *iflag = perm + 2 * chi;                                // [4]
-    unsigned char *bond = reinterpret_cast<unsigned char *>(iflag + 4);  // [L+1]
-    unsigned char *mq = bond + (L + 1);                                // [L]
-
-    T *C = regA;                     // [2][chi][chi]
-    T *R = regA + 2 * chi * chi;     // [2][chi][chi]
-    T *Mb = regB;                    // [2][2chi][ldm]
-    T *Qb = regA;                    // [2][2chi][chi] (reuses C and R)
-    T *X = Wm;                       // [2chi][chi] lives in Wm between sites
+    const int regA_sz = 4 * cc2 + 4 * chi * ldm;                   // QR phase
+    const int regS_sz = 4 * bst + 2 * cc2;                         // SVD phase
+    T *reg = reinterpret_cast<T *>(smem);
+    T *C = reg;                       // [chi][chi]
+    T *R = reg + cc2;                 // [2][chi][chi]
+    T *Qb = reg;                      // [2][2chi][chi]  (over C and R)
+    T *Mb = reg + 4 * cc2;            // [2][2chi][ldm]
+    T *Tm = reg;                      // [2][chi+1][ldt]
+    T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
+    T *X = reg + 4 * bst;             // [2][chi][chi]
+    T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
+    T *tau = tail;                    // [2][chi]
+    T *nrm = tau + 2 * chi;           // [2][chi+2]
+    T *cn2 = nrm + 2 * (chi + 2);     // [2][chi+2]
+    T *smallv = cn2 + 2 * (chi + 2);  // [2]
+    double *red = reinterpret_cast<double *>(smallv + 2 + ((2 * chi + 2 * (chi + 2) * 2 + 2) & 1));
+    double *uvec = red + NT / 64;     // [2][64] row-0 contraction vector
+    double *scal = uvec + 128;        // [8]
+    int *colof = reinterpret_cast<int *>(scal + 8);   // [2chi+4] kept column of new bond slot
+    int *rankv = colof + 2 * chi + 4;                 // [2chi+4]
+    int *iflag = rankv + 2 * chi + 4;                 // [4]
+    unsigned char *dsec = reinterpret_cast<unsigned char *>(iflag + 4);  // [L+1][2] bond sectors
+    unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
 
     int total_sweeps = 0;
     long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0;   // wall-clock ticks per phase
 
-    // ---- bottom row (row L-1): bond dimension 2, bonds carry the spin ------
+    // write one parity-basis site (from a generator) to the ping-pong buffer
+    // and its spin-basis form to the cache
+    auto put_site = [&](int r, int c, int a, int b, T e0, T e1) {
+        T *ps = prev + (size_t)(r & 1) * row_sz + (size_t)c * site_sz;
+        S *cs = cache + (size_t)r * row_sz + (size_t)c * site_sz;
+        ps[a * chi + b] = e0;
+        ps[cc2 + a * chi + b] = e1;
+        cs[a * chi + b] = store_as<S, T>((e0 + e1) * RS2);
+        cs[cc2 + a * chi + b] = store_as<S, T>((e0 - e1) * RS2);
+    };
+
+    // ---- bottom row (row L-1): every inner bond is (1 even, 1 odd) ---------
     {
         const int r = L - 1;
-        S *crow = cache + (size_t)r * row_sz;
-        T *prow = kPingPong ? prev + (size_t)(r & 1) * row_sz : nullptr;
-        for (size_t e = tid; e < row_sz; e += NT) {
-            const int c = (int)(e / site_sz);
-            const int rem = (int)(e % site_sz);
-            const int s = rem / (chi * chi), a = (rem / chi) % chi, b = rem % chi;
-            double v = 0.0;
+        for (size_t e = tid; e < (size_t)L * cc2; e += NT) {
+            const int c = (int)(e / cc2), a = (int)((e / chi) % chi), b = (int)(e % chi);
+            T v0 = 0, v1 = 0;   // physical parity 0 / 1
             if (c == 0) {
-                v = (a == 0 && b == s) ? 1.0 : 0.0;
-            } else {
-                double same, diff;
-                boltz(beta, jh[(size_t)r * (L - 1) + (c - 1)], same, diff);
-                const double bl = (a == s) ? same : diff;       // Bh(c-1)[l=a, s]
-                if (a < 2) {
-                    if (c == L - 1) v = (b == 0) ? bl : 0.0;
-                    else v = (b == s) ? bl : 0.0;
+                if (a == 0 && b == 0) v0 = 1;
+                if (a == 0 && b == 1) v1 = 1;
+            } else if (a < 2) {
+                double l0, l1;
+                lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], l0, l1);
+                const T lh = (T)(a == 0 ? l0 : l1);
+                if (c == L - 1) {
+                    if (b == 0) { if (a == 0) v0 = lh; else v1 = lh; }
+                } else if (b < 2) {
+                    // parity of (l, s, t) even: s = l ^ t
+                    if ((a ^ b) == 0) v0 = lh; else v1 = lh;
                 }
             }
-            crow[e] = store_as<S, T>((T)v);
-            if (kPingPong) prow[e] = (T)v;
+            put_site(r, c, a, b, v0, v1);
         }
-        for (int i = tid; i <= L; i += NT) bond[i] = (i == 0 || i == L) ? 1 : 2;
+        for (int i = tid; i <= L; i += NT) {
+            dsec[2 * i] = 1;
+            dsec[2 * i + 1] = (i == 0 || i == L) ? 0 : 1;
+        }
         double part = 0.0;
         for (int c = tid; c < L - 1; c += NT) part += beta * fabs((double)jh[(size_t)r * (L - 1) + c]);
-        const double ls = block_sum(part, red);
+        const double ls = block_sum(part, red) - (double)(L - 2) * 0.5 * LN2;
         if (tid == 0) lsc[r] = ls;
         __syncthreads();
     }
 
-    double logz_tail = 0.0;   // ln of the row-0 contraction (thread 0)
+    double logz_tail = 0.0;   // (thread 0) ln of the row-0 contraction
 
     for (int r = L - 2; r >= 0; --r) {
-        const S *orow_s = cache + (size_t)(r + 1) * row_sz;
-        const T *orow_t = kPingPong ? prev + (size_t)((r + 1) & 1) * row_sz : nullptr;
-        S *crow = cache + (size_t)r * row_sz;
-        T *prow = kPingPong ? prev + (size_t)(r & 1) * row_sz : nullptr;
+        const T *orow = prev + (size_t)((r + 1) & 1) * row_sz;
 
         double part = 0.0;
         for (int c = tid; c < L; c += NT) {
             part += beta * fabs((double)jv[(size_t)r * L + c]);
             if (c < L - 1) part += beta * fabs((double)jh[(size_t)r * (L - 1) + c]);
         }
-        double ls = block_sum(part, red);   // valid in every thread; thread 0 keeps it
+        double ls = block_sum(part, red) - (double)(L - 1) * LN2;
 
         // ================= QR sweep, left to right =========================
         const long long tq0 = wall_clock64();
-        int mp = 1;                           // m_{c-1}
+        if (tid == 0) { mq[0] = 1; mq[1] = 0; }
+        __syncthreads();
         for (int c = 0; c < L; ++c) {
-            const int Dp = bond[c], D = bond[c + 1];
-            const int K = (c == 0) ? 1 : 2 * mp;
-            double vs, vd;
-            boltz(beta, jv[(size_t)r * L + c], vs, vd);
-            // (a) C_s = sum_n Bv[s][n] A_old[n]   (Dp x D)
-            const size_t obase = (size_t)c * site_sz;
-            for (int e = tid; e < 2 * Dp * D; e += NT) {
-                const int s = e / (Dp * D), b = (e / D) % Dp, bb = e % D;
-                const size_t i0 = obase + (size_t)s * chi * chi + b * chi + bb;
-                const size_t i1 = obase + (size_t)(1 - s) * chi * chi + b * chi + bb;
-                T a0, a1;
-                if (kPingPong) { a0 = orow_t[i0]; a1 = orow_t[i1]; }
-                else { a0 = load_as<T, S>(orow_s + i0); a1 = load_as<T, S>(orow_s + i1); }
-                C[s * chi * chi + b * chi + bb] = (T)vs * a0 + (T)vd * a1;
+            const int pa0 = dsec[2 * c], Dp = pa0 + dsec[2 * c + 1];             // old left bond
+            const int pb0 = dsec[2 * (c + 1)], D = pb0 + dsec[2 * (c + 1) + 1];  // old right bond
+            const int m0 = mq[2 * c], m1 = mq[2 * c + 1];
+            const int K = m0 + m1;
+            double lv0, lv1;
+            lam_of(beta, jv[(size_t)r * L + c], lv0, lv1);
+            // (a) C[a][b] = lam_v[pa^pb] * A_old[pa^pb][a][b]
+            const T *os = orow + (size_t)c * site_sz;
+            for (int e = tid; e < Dp * D; e += NT) {
+                const int a = e / D, b = e % D;
+                const int n = (a >= pa0) ^ (b >= pb0);
+                C[a * chi + b] = (T)(n ? lv1 : lv0) * os[n * cc2 + a * chi + b];
             }
             __syncthreads();
-            // (b) M_s[(t,j)][b'] = Bh(c-1)[t][s] * (R_t C_s)[j][b']
+            // (b) M^p rows: sigma=0 -> Rh^p C (m_p rows), sigma=1 -> Rh^(1-p) C
+            const int nblk = (c == L - 1) ? 1 : 2;
             if (c == 0) {
                 for (int e = tid; e < 2 * D; e += NT) {
-                    const int s = e / D, bb = e % D;
-                    Mb[s * 2 * chi * ldm + bb] = C[s * chi * chi + bb];
+                    const int p = e / D, b = e % D;
+                    Mb[p * 2 * chi * ldm + b] = C[b];
                 }
             } else {
-                double hs, hd;
-                boltz(beta, jh[(size_t)r * (L - 1) + (c - 1)], hs, hd);
-                for (int e = tid; e < 2 * K * D; e += NT) {
-                    const int s = e / (K * D), row = (e / D) % K, bb = e % D;
-                    const int t = row / mp, j = row % mp;
-                    const T *Rt = R + t * chi * chi + j * chi;
-                    const T *Cs = C + s * chi * chi + bb;
-                    T acc = 0;
-                    for (int b = j; b < Dp; ++b) acc += Rt[b] * Cs[b * chi];   // R_t upper trapezoidal
-                    Mb[s * 2 * chi * ldm + row * ldm + bb] = (T)((t == s) ? hs : hd) * acc;
+                double lh0, lh1;
+                lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], lh0, lh1);
+                for (int e = tid; e < nblk * K * D; e += NT) {
+                    const int p = e / (K * D), row = (e / D) % K, b = e % D;
+                    const int q = (row < (p == 0 ? m0 : m1)) ? p : 1 - p;      // R block of this row
+                    const int k = (q == p) ? row : row - (p == 0 ? m0 : m1);
+                    const T *Rq = R + q * cc2 + k * chi;
+                    T acc0 = 0, acc1 = 0;   // columns a in sector q (l = 0) / sector 1-q (l = 1)
+                    for (int a = k; a < Dp; ++a) {
+                        const T v = Rq[a] * C[a * chi + b];
+                        if ((a >= pa0) == (q == 1)) acc0 += v; else acc1 += v;
+                    }
+                    Mb[p * 2 * chi * ldm + row * ldm + b] = (T)lh0 * acc0 + (T)lh1 * acc1;
                 }
             }
             __syncthreads();
             if (c == L - 1) {
-                // center of the sweep: T_last[row][s] = M_s[row][0]  (D == 1)
-                T *q = qscr + (size_t)c * 2 * 2 * chi * chi;
-                for (int e = tid; e < 2 * K; e += NT) {
-                    const int row = e >> 1, s = e & 1;
-                    q[row * 2 + s] = Mb[s * 2 * chi * ldm + row * ldm];
-                }
+                // the center: single block, K x 1, kept for the SVD sweep
+                T *q = qscr + (size_t)c * 4 * cc2;
+                for (int e = tid; e < K; e += NT) q[e] = Mb[e * ldm];
+                if (tid == 0) { mq[2 * L] = 1; mq[2 * L + 1] = 0; }
                 __syncthreads();
                 break;
             }
@@ -309,27 +370,23 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
             if (G > 64) G = 64;
             const int grp = ht / G, gl = ht % G, ngrp = 128 / G;
             for (int j = 0; j < mc; ++j) {
+                // reflector of column j, computed and applied to the column by
+                // the first wave of the block's half (no barrier in between)
                 if (ht < 64) {
                     T sum = 0;
                     for (int i = j + 1 + ht; i < K; i += 64) { const T x = M[i * ldm + j]; sum += x * x; }
                     sum = group_sum(sum, 64);
-                    if (ht == 0) {
-                        const T x0 = M[j * ldm + j];
-                        T tj = 0, sc = 0;
-                        if (sum != (T)0) {
-                            const T nr = sqrt(x0 * x0 + sum);
-                            const T be = x0 >= 0 ? -nr : nr;
-                            tj = (be - x0) / be;
-                            sc = (T)1 / (x0 - be);
-                            M[j * ldm + j] = be;
-                        }
-                        tau[half * chi + j] = tj;
-                        scal[half] = (double)sc;
+                    const T x0 = M[j * ldm + j];
+                    T tj = 0, sc = 0, be = x0;
+                    if (sum != (T)0) {
+                        const T nr = sqrt(x0 * x0 + sum);
+                        be = x0 >= 0 ? -nr : nr;
+                        tj = (be - x0) / be;
+                        sc = (T)1 / (x0 - be);
                     }
+                    for (int i = j + 1 + ht; i < K; i += 64) M[i * ldm + j] *= sc;
+                    if (ht == 0) { M[j * ldm + j] = be; tau[half * chi + j] = tj; }
                 }
-                __syncthreads();
-                const T sc = (T)scal[half];
-                for (int i = j + 1 + ht; i < K; i += 128) M[i * ldm + j] *= sc;
                 __syncthreads();
                 const T tj = tau[half * chi + j];
                 if (tj != (T)0) {
@@ -342,16 +399,16 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                 }
                 __syncthreads();
             }
-            // (d) explicit Q (K x mc) into Qb[half], by backward accumulation
+            // (d) explicit Q^p (K x mc) in Qb[half]; (e) copy to scratch slot c
             {
-                T *Q = Qb + half * 2 * chi * chi;
+                T *Q = Qb + half * 2 * cc2;
                 for (int e = ht; e < K * mc; e += 128) { const int i = e / mc, k = e % mc; Q[i * chi + k] = (i == k) ? (T)1 : (T)0; }
                 __syncthreads();
                 int Gq = pow2_floor(128 / mc);
                 if (Gq > 64) Gq = 64;
                 const int gq = ht / Gq, lq = ht % Gq, nq = 128 / Gq;
-                // each group owns the same columns for every j (no barrier
-                // between reflectors is needed because columns never change hands)
+                // each group owns the same columns for every j, so columns
+                // never change hands between reflectors
                 for (int j = mc - 1; j >= 0; --j) {
                     const T tj = tau[half * chi + j];
                     if (tj == (T)0) continue;
@@ -364,141 +421,181 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                     }
                 }
                 __syncthreads();
-                // (e) write Q_s to scratch slot c: [s][2chi][chi]
-                T *q = qscr + (size_t)c * 2 * 2 * chi * chi + half * 2 * chi * chi;
+                T *q = qscr + (size_t)c * 4 * cc2 + half * 2 * cc2;
                 for (int e = ht; e < K * mc; e += 128) { const int i = e / mc, k = e % mc; q[i * chi + k] = Q[i * chi + k]; }
                 __syncthreads();
             }
-            // (f) R_s (mc x D, upper trapezoidal) becomes the carried R_t; normalise
+            // (f) R^p (mc x D, upper trapezoidal) carried right; joint normalisation
             double rp = 0.0;
             for (int e = tid; e < 2 * mc * D; e += NT) {
-                const int s = e / (mc * D), j = (e / D) % mc, k = e % D;
-                const T v = (k >= j) ? Mb[s * 2 * chi * ldm + j * ldm + k] : (T)0;
-                R[s * chi * chi + j * chi + k] = v;
+                const int p = e / (mc * D), j = (e / D) % mc, k = e % D;
+                const T v = (k >= j) ? Mb[p * 2 * chi * ldm + j * ldm + k] : (T)0;
+                R[p * cc2 + j * chi + k] = v;
                 rp += (double)v * (double)v;
             }
-            const double nu2 = block_sum(rp, red);
-            const double nu = sqrt(nu2);
+            const double nu = sqrt(block_sum(rp, red));
             ls += log(nu);
             const T inv = (T)(1.0 / nu);
             for (int e = tid; e < 2 * mc * D; e += NT) {
-                const int s = e / (mc * D), j = (e / D) % mc, k = e % D;
-                R[s * chi * chi + j * chi + k] *= inv;
+                const int p = e / (mc * D), j = (e / D) % mc, k = e % D;
+                R[p * cc2 + j * chi + k] *= inv;
             }
-            if (tid == 0) mq[c] = (unsigned char)mc;
-            mp = mc;
+            if (tid == 0) { mq[2 * (c + 1)] = (unsigned char)mc; mq[2 * (c + 1) + 1] = (unsigned char)mc; }
             __syncthreads();
         }
 
         // ================= SVD sweep, right to left ========================
         const long long ts0 = wall_clock64();
         cyc_qr += ts0 - tq0;
-        int kr = 1;                           // k'_{c+1}
-        if (r == 0 && tid == 0) uvec[0] = 1.0;
+        if (tid == 0) { dsec[2 * L] = 1; dsec[2 * L + 1] = 0; uvec[0] = 1.0; }
+        __syncthreads();
         double ulog = 0.0;
         for (int c = L - 1; c >= 0; --c) {
-            const int K = (c == 0) ? 1 : 2 * mq[c - 1];
-            const T *q = qscr + (size_t)c * 2 * 2 * chi * chi;
+            const int r0 = dsec[2 * (c + 1)], r1 = dsec[2 * (c + 1) + 1];   // right bond sectors
+            const int kr = r0 + r1;
+            const int K0 = mq[2 * c], K1 = mq[2 * c + 1];                  // left (QR) bond sectors
+            const T *q = qscr + (size_t)c * 4 * cc2;
             if (c == 0) {
-                // site 0: T0[s][m] = Q_s(0)[0][0] * X[s][m]
+                // site 0: one row (even), columns (s=0, m even) and (s=1, m odd)
                 double sp = 0.0;
-                for (int e = tid; e < 2 * kr; e += NT) {
-                    const int s = e / kr, m = e % kr;
-                    const T v = q[s * 2 * chi * chi] * X[s * chi + m];
-                    nrm[e] = v;
-                    sp += (double)v * (double)v;
+                for (int m = tid; m < kr; m += NT) {
+                    const int p = (m >= r0);                    // sector of m; physical s = p
+                    const int mm = p ? m - r0 : m;
+                    const int mcq = mq[2 * (c + 1) + p];        // QR bond c|c+1 sector p
+                    const T *qrow = q + p * 2 * cc2;            // Q^p, sigma = p part starts at row 0
+                    T acc = 0;
+                    for (int j = 0; j < mcq; ++j) acc += qrow[j] * X[p * cc2 + j * chi + mm];
+                    nrm[m] = acc;
+                    sp += (double)acc * (double)acc;
                 }
                 const double n0 = sqrt(block_sum(sp, red));
                 ls += log(n0);
                 const T inv = (T)(1.0 / n0);
-                S *site = crow;
-                T *psite = kPingPong ? prow : nullptr;
-                for (size_t e = tid; e < site_sz; e += NT) {
-                    const int s = (int)(e / (chi * chi)), a = (int)((e / chi) % chi), m = (int)(e % chi);
-                    const T v = (a == 0 && m < kr) ? nrm[s * kr + m] * inv : (T)0;
-                    site[e] = store_as<S, T>(v);
-                    if (kPingPong) psite[e] = v;
+                for (int e = tid; e < cc2; e += NT) {
+                    const int a = e / chi, m = e % chi;
+                    T v0 = 0, v1 = 0;
+                    if (a == 0 && m < kr) { if (m < r0) v0 = nrm[m] * inv; else v1 = nrm[m] * inv; }
+                    put_site(r, 0, a, m, v0, v1);
                 }
                 if (r == 0 && tid == 0) {
                     double tot = 0.0;
-                    for (int s = 0; s < 2; ++s)
-                        for (int m = 0; m < kr; ++m) tot += (double)nrm[s * kr + m] * (double)inv * uvec[m];
-                    logz_tail = ulog + log(tot);
+                    for (int m = 0; m < r0; ++m) tot += (double)nrm[m] * (double)inv * uvec[m];
+                    logz_tail = ulog + log(tot) + (double)L * 0.5 * LN2;
                 }
-                if (tid == 0) bond[0] = 1;
+                if (tid == 0) { dsec[0] = 1; dsec[1] = 0; }
                 __syncthreads();
                 break;
             }
-            int n;
+            const int n = (kr + 1) & ~1;     // columns per block, padded even
+            // T^p[k][idx]: idx < d^p -> (s=0, m = off_p + idx); else (s=1, m = off_(1-p) + idx - d^p)
             if (c == L - 1) {
-                n = 2;
-                for (int e = tid; e < 2 * K; e += NT) { const int row = e >> 1, s = e & 1; Tm[s * ldt + row] = q[row * 2 + s]; }
+                for (int e = tid; e < 2 * n * ldt; e += NT) Tm[(e / (n * ldt)) * bst + e % (n * ldt)] = 0;
+                __syncthreads();
+                for (int e = tid; e < K0 + K1; e += NT) {
+                    const int p = e >= K0, k = p ? e - K0 : e;
+                    Tm[p * bst + k] = q[e];
+                }
             } else {
-                const int mc = mq[c];
-                n = 2 * kr;
-                for (int e = tid; e < K * n; e += NT) {
-                    const int col = e / K, row = e % K;
-                    const int s = col / kr, m = col % kr;
-                    const T *qr = q + s * 2 * chi * chi + row * chi;
-                    const T *xc = X + (s * mc) * chi + m;
+                const int mn0 = mq[2 * (c + 1)], mn1 = mq[2 * (c + 1) + 1];   // QR bond c|c+1 sectors
+                for (int e = tid; e < 2 * n * chi; e += NT) {
+                    const int p = e / (n * chi), idx = (e / chi) % n, k = e % chi;
+                    const int Kp = p ? K1 : K0;
                     T acc = 0;
-                    for (int j = 0; j < mc; ++j) acc += qr[j] * xc[j * chi];
-                    Tm[col * ldt + row] = acc;
+                    if (k < Kp && idx < kr) {
+                        const int dp = p ? r1 : r0;
+                        int qb, rowoff, xb, xc, mcq;
+                        if (idx < dp) { qb = p; rowoff = 0; xb = p; xc = idx; }
+                        else { qb = 1 - p; rowoff = qb ? K0 : K1; xb = 1 - p; xc = idx - dp; }
+                        // rows of Q^qb: sigma=0 part (K_qb rows) first, then sigma=1 part
+                        rowoff = (idx < dp) ? 0 : (qb == 0 ? K0 : K1);
+                        mcq = xb ? mn1 : mn0;
+                        const T *qr = q + qb * 2 * cc2 + (rowoff + k) * chi;
+                        const T *xr = X + xb * cc2 + xc;
+                        for (int j = 0; j < mcq; ++j) acc += qr[j] * xr[j * chi];
+                    }
+                    Tm[p * bst + idx * ldt + k] = acc;
                 }
             }
             __syncthreads();
-            for (int e = tid; e < n * n; e += NT) { const int col = e / n, row = e % n; Wm[col * ldt + row] = (row == col) ? (T)1 : (T)0; }
+            for (int e = tid; e < 2 * n * n; e += NT) {
+                const int p = e / (n * n), col = (e / n) % n, row = e % n;
+                Wm[p * bst + col * ldt + row] = (row == col) ? (T)1 : (T)0;
+            }
             __syncthreads();
             {
                 const long long t0 = wall_clock64();
-                total_sweeps += jacobi<T>(Tm, Wm, ldt, K, n, nrm, iflag);
+                total_sweeps += jacobi2<T>(Tm, Wm, ldt, bst, K0, K1, n, cn2, smallv, iflag);
                 cyc_jac += wall_clock64() - t0;
             }
-            // singular values and their order
-            for (int col = tid; col < n; col += NT) {
+            // singular values of both blocks (padding columns and empty blocks excluded)
+            for (int e = tid; e < 2 * n; e += NT) {
+                const int p = e / n, col = e % n, Kp = p ? K1 : K0;
                 T s2 = 0;
-                for (int row = 0; row < K; ++row) { const T v = Tm[col * ldt + row]; s2 += v * v; }
-                nrm[col] = sqrt(s2);
+                if (col < kr) for (int k = 0; k < Kp; ++k) { const T v = Tm[p * bst + col * ldt + k]; s2 += v * v; }
+                nrm[e] = (col < kr && Kp > 0) ? sqrt(s2) : (T)-1;
             }
             __syncthreads();
-            for (int col = tid; col < n; col += NT) {
-                const T v = nrm[col];
+            int kk = chi < K0 + K1 ? chi : K0 + K1;
+            if (2 * kr < kk) kk = 2 * kr;
+            for (int e = tid; e < 2 * n; e += NT) {
+                const T v = nrm[e];
                 int rk = 0;
-                for (int o = 0; o < n; ++o) { const T w = nrm[o]; rk += (w > v) || (w == v && o < col); }
-                perm[rk] = col;
+                for (int o = 0; o < 2 * n; ++o) { const T w = nrm[o]; rk += (w > v) || (w == v && o < e); }
+                rankv[e] = (v >= (T)0) ? rk : 1 << 20;
             }
             __syncthreads();
-            int kk = chi < K ? chi : K;
-            if (n < kk) kk = n;
-            double kp = 0.0;
-            for (int i = tid; i < kk; i += NT) { const double v = (double)nrm[perm[i]]; kp += v * v; }
-            const double nk = sqrt(block_sum(kp, red));
-            ls += log(nk);
-            // new site c = V^T[:kk], shape (kk, 2, kr), zero padded
-            {
-                S *site = crow + (size_t)c * site_sz;
-                T *psite = kPingPong ? prow + (size_t)c * site_sz : nullptr;
-                for (size_t e = tid; e < site_sz; e += NT) {
-                    const int s = (int)(e / (chi * chi)), a = (int)((e / chi) % chi), m = (int)(e % chi);
-                    const T v = (a < kk && m < kr) ? Wm[perm[a] * ldt + s * kr + m] : (T)0;
-                    site[e] = store_as<S, T>(v);
-                    if (kPingPong) psite[e] = v;
+            // new left bond: kept columns of block 0 (by rank), then of block 1
+            if (tid == 0) {
+                int s0 = 0, s1 = 0;
+                for (int e = 0; e < 2 * n; ++e) if (rankv[e] < kk) { if (e < n) ++s0; else ++s1; }
+                iflag[1] = s0; iflag[2] = s1;
+            }
+            __syncthreads();
+            const int s0 = iflag[1];
+            for (int e = tid; e < 2 * n; e += NT) {
+                if (rankv[e] < kk) {
+                    const int p = e / n;
+                    int pos = 0;
+                    for (int o = p * n; o < p * n + n; ++o) pos += rankv[o] < rankv[e];
+                    colof[(p ? s0 : 0) + pos] = e;
                 }
             }
+            double kp = 0.0;
+            for (int e = tid; e < 2 * n; e += NT) if (rankv[e] < kk) { const double v = (double)nrm[e]; kp += v * v; }
+            const double nk = sqrt(block_sum(kp, red));   // (block_sum syncs)
+            ls += log(nk);
+            // new site c (right-canonical): slot a <- column colof[a]
+            for (int e = tid; e < cc2; e += NT) {
+                const int a = e / chi, m = e % chi;
+                T v0 = 0, v1 = 0;
+                if (a < kk && m < kr) {
+                    const int ce = colof[a], p = ce / n, col = ce % n;
+                    const int pm = m >= r0, mm = pm ? m - r0 : m;
+                    const int dp = p ? r1 : r0;
+                    // physical parity s = p ^ pm; row of W^p for (s, m)
+                    const int s = p ^ pm;
+                    const int row = (s == 0) ? mm : dp + mm;
+                    const T w = Wm[p * bst + col * ldt + row];
+                    if (s == 0) v0 = w; else v1 = w;
+                }
+                put_site(r, c, a, m, v0, v1);
+            }
             if (r == 0) {
-                // row-0 contraction from the right: u[a] <- sum_s sum_m A_c[s][a][m] u[m]
+                // row-0 contraction from the right on the even physical component
                 double *u = uvec, *un = uvec + 64;
                 for (int a = tid; a < kk; a += NT) {
+                    const int ce = colof[a], p = ce / n, col = ce % n;
                     double acc = 0.0;
-                    for (int s = 0; s < 2; ++s)
-                        for (int m = 0; m < kr; ++m) acc += (double)Wm[perm[a] * ldt + s * kr + m] * u[m];
+                    // s = 0 entries: m in sector p, row = index within the sector
+                    const int dp = p ? r1 : r0, off = p ? r0 : 0;
+                    for (int mm = 0; mm < dp; ++mm) acc += (double)Wm[p * bst + col * ldt + mm] * u[off + mm];
                     un[a] = acc;
                 }
                 __syncthreads();
                 if (tid == 0) {
                     double mx = 0.0;
                     for (int a = 0; a < kk; ++a) mx = fmax(mx, fabs(un[a]));
-                    scal[2] = mx;
+                    scal[2] = mx > 0.0 ? mx : 1.0;
                 }
                 __syncthreads();
                 const double mx = scal[2];
@@ -506,14 +603,17 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                 ulog += log(mx);
             }
             __syncthreads();
-            // X (K x kk) = U S / ||S_kept||, kept in the Wm region for the next site
+            // X^p (K_p x d'^p) = U S / ||S_kept|| for the next site
             const T inv = (T)(1.0 / nk);
-            for (int e = tid; e < K * kk; e += NT) {
-                const int row = e / kk, a = e % kk;
-                X[row * chi + a] = Tm[perm[a] * ldt + row] * inv;
+            for (int e = tid; e < 2 * chi * chi; e += NT) {
+                const int p = e / cc2, k = (e / chi) % chi, j = e % chi;
+                const int Kp = p ? K1 : K0, dp = p ? kk - s0 : s0;
+                if (k < Kp && j < dp) {
+                    const int ce = colof[(p ? s0 : 0) + j];
+                    X[e] = Tm[p * bst + (ce % n) * ldt + k] * inv;
+                }
             }
-            if (tid == 0) bond[c] = (unsigned char)kk;
-            kr = kk;
+            if (tid == 0) { dsec[2 * c] = (unsigned char)s0; dsec[2 * c + 1] = (unsigned char)(kk - s0); }
             __syncthreads();
         }
         cyc_svd += wall_clock64() - ts0;
@@ -549,15 +649,17 @@ template hipError_t launch_build<float, float>(const InstDesc *, unsigned char *
 template hipError_t launch_build<float, __hip_bfloat16>(const InstDesc *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
 template hipError_t launch_build<float, __half>(const InstDesc *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
 
-// Shared-memory bytes the build kernel needs for bond dimension chi.
+// Shared-memory bytes the build kernel needs for bond dimension chi and side L.
 size_t build_lds_bytes(int chi, int L, size_t tsize) {
-    size_t elems = (size_t)4 * chi * (2 * chi + 1);          // Tm + Wm (>= C,R + M)
-    elems += 2 * chi + 2 * chi;                              // tau, nrm
+    const size_t regA = (size_t)4 * chi * chi + (size_t)4 * chi * (chi + 1);
+    const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi;
+    size_t elems = (regA > regS ? regA : regS);
+    elems += 2 * chi + 2 * (chi + 2) + 2 * (chi + 2) + 2 + 1;     // tau, nrm, cn2, small, align
     size_t bytes = elems * tsize;
     bytes = (bytes + 7) & ~(size_t)7;
-    bytes += (NT / 64 + 128 + 4) * sizeof(double);           // red, uvec, scal
-    bytes += (2 * chi + 4) * sizeof(int);                    // perm, iflag
-    bytes += (size_t)(L + 1) + L;                            // bond, mq
+    bytes += (NT / 64 + 128 + 8) * sizeof(double);           // red, uvec, scal
+    bytes += (2 * (2 * chi + 4) + 4) * sizeof(int);          // colof, rankv, iflag
+    bytes += (size_t)4 * (L + 1);                            // dsec, mq
     return (bytes + 15) & ~(size_t)15;
 }
 
