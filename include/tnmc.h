@@ -95,15 +95,24 @@ typedef struct tnmc_chain {
 
 typedef struct tnmc_env tnmc_env;   /* opaque; host metadata into workspace */
 
-/* Learned proposal correction: a 3-layer tanh MLP (width 64) whose output is
- * added to every site's TN logit.  Weights are device float32 arrays, row
- * major [out][in]; layer 1 takes TNMC_MLP_IN features (see tnmc_sample).   */
+/* Learned proposal correction (not part of the paper's method; the exact
+ * Metropolis step of Eq. (10) keeps sampling unbiased whatever it does).
+ * A 3-layer tanh MLP, widths 64/64/1, adds a correction d to every site's
+ * TN logit.  Its 64 input features at site (r,c) are: the horizontal
+ * couplings of rows r-2..r+2, columns c-2..c+1 (20), the vertical couplings
+ * of rows r-2..r+1, columns c-2..c+2 (20), the already-sampled spins of rows
+ * r-2, r-1 at columns c-2..c+2 (10) and of row r at c-2, c-1 (2), the TN
+ * logit clipped to [-30,30] and divided by 8 (1), zeros (11); every slot
+ * outside the lattice is zero.  Parameters are one float32 vector of
+ * TNMC_MLP_NPARAM values, row-major [out][in]:
+ *   W1 [64][64] | b1 [64] | W2 [64][64] | b2 [64] | W3 [64] | b3 [1]
+ * Inference inside tnmc_sample rounds the weights to bfloat16 and
+ * accumulates in float32.                                                 */
 #define TNMC_MLP_IN     64
 #define TNMC_MLP_HIDDEN 64
+#define TNMC_MLP_NPARAM 8385
 typedef struct tnmc_mlp {
-    const float *W1, *b1;   /* [64][64], [64] */
-    const float *W2, *b2;   /* [64][64], [64] */
-    const float *W3, *b3;   /* [64],     [1]  */
+    const float *params;    /* device float [TNMC_MLP_NPARAM] */
 } tnmc_mlp;
 
 /* Bytes of workspace tnmc_build_env + tnmc_sample need for this problem at
@@ -132,7 +141,8 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision,
  *                packed layout to be scored (teacher forcing): the sampler
  *                evaluates their log q and logits instead of drawing.
  *  mlp           NULL for the plain TN proposal, else the learned
- *                correction added to every logit before the draw.
+ *                correction added to every logit before the draw
+ *                (TNMC_FP32 envs with chi <= 16; TNMC_ENOTSUP otherwise).
  *  spins_out     device uint64, packed layout (may equal forced_spins).
  *  logq_out      device double [B][n_samples]: log q of each configuration.
  *  logits_out    device float [B][n_samples][L_i*L_i] or NULL: the logit of
@@ -168,6 +178,39 @@ int tnmc_accept(int32_t batch, int32_t n_samples, const double *logq,
                 uint64_t seed, uint64_t step_offset, uint8_t *accepted_out,
                 int64_t *state_out, void *stream);
 
+/* Features of every site of n_samples configurations per instance of the
+ * env (layout above), for training the learned correction.
+ *  spins      device, packed layout
+ *  logits_lo  device float [B][n_samples][L_i*L_i]: the TN logits of the
+ *             same configurations (tnmc_sample's logits_out)
+ *  feat_out   device float [B][n_samples][L_i*L_i][64]                      */
+int tnmc_mlp_features(const tnmc_env *env, int32_t n_samples, const uint64_t *spins,
+                      const float *logits_lo, float *feat_out, void *stream);
+
+/* Floats of scratch tnmc_mlp_train_step needs for n_rows rows.            */
+size_t tnmc_mlp_scratch_floats(int32_t n_rows);
+
+/* One optimisation step of the learned correction on n_rows feature rows.
+ * Loss: mean over rows of the cross-entropy between sigmoid(logit_lo + d)
+ * and the soft target sigmoid(target_logit).  The gradient is summed in a
+ * fixed order (deterministic).  With step >= 1 an Adam update (Kingma & Ba;
+ * beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with this step number)
+ * is applied to params / adam_m / adam_v (device float [TNMC_MLP_NPARAM]);
+ * with step == 0 nothing is updated.
+ *  grad_out   device float [TNMC_MLP_NPARAM] or NULL: the mean gradient
+ *  loss_out   device float [1] or NULL: the mean loss before the update
+ *  scratch    device float [tnmc_mlp_scratch_floats(n_rows)]              */
+int tnmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t n_rows,
+                        const float *feat, const float *logit_lo, const float *target_logit,
+                        float lr, int32_t step, float *scratch, float *grad_out,
+                        float *loss_out, void *stream);
+
+/* The correction d for n_rows feature rows (device float [n_rows]); with
+ * bf16_weights != 0 the weights are first rounded to bfloat16, as inside
+ * tnmc_sample.                                                            */
+int tnmc_mlp_forward(const float *params, int32_t n_rows, const float *feat,
+                     int32_t bf16_weights, float *d_out, void *stream);
+
 /* Release an env (host memory only; the workspace stays the caller's).    */
 void tnmc_free_env(tnmc_env *env);
 
@@ -181,11 +224,15 @@ int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
                         uint32_t c2, uint32_t stream_id, int32_t n,
                         double *out, void *stream);
 
-/* Build statistics of this env (device int64 [B][4], valid once the build
- * has completed on its stream): per instance the total number of Jacobi
- * sweeps over all truncations, then the wall-clock ticks (100 MHz device
- * counter) spent in the QR sweeps, in the SVD sweeps, and inside the Jacobi
- * iterations of those SVD sweeps.  NULL for a NULL env.                    */
+/* Statistics of this env (device int64 [B][8], valid once the work has
+ * completed on its stream), per instance: the total number of Jacobi sweeps
+ * over all truncations; wall-clock ticks (100 MHz device counter) spent in
+ * the QR sweeps, in the SVD sweeps, and inside the Jacobi iterations of the
+ * SVD sweeps; the ticks at which the instance's build started and ended;
+ * the tick at which the first sample tile of the last tnmc_sample call
+ * ended (the only tile when n_samples <= 256); one spare slot.  The build
+ * processes instances in decreasing order of estimated cost (L-1) L chi^3.
+ * NULL for a NULL env.                                                    */
 const int64_t *tnmc_env_stats(const tnmc_env *env);
 
 #ifdef __cplusplus

@@ -35,12 +35,17 @@ class _Problem(ctypes.Structure):
 
 
 class _Mlp(ctypes.Structure):
-    _fields_ = [("W1", c_void_p), ("b1", c_void_p), ("W2", c_void_p), ("b2", c_void_p),
-                ("W3", c_void_p), ("b3", c_void_p)]
+    _fields_ = [("params", c_void_p)]
+
+
+MLP_NPARAM = 8385
+MLP_LAYOUT = {"W1": (0, (64, 64)), "b1": (4096, (64,)), "W2": (4160, (64, 64)), "b2": (8256, (64,)),
+              "W3": (8320, (64,)), "b3": (8384, (1,))}
 
 
 EXPORTS = ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy", "tnmc_accept",
-           "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats")
+           "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats",
+           "tnmc_mlp_features", "tnmc_mlp_scratch_floats", "tnmc_mlp_train_step", "tnmc_mlp_forward")
 
 
 def load(path: str = LIB_PATH):
@@ -66,8 +71,15 @@ def load(path: str = LIB_PATH):
                                         c_void_p, c_void_p]
     lib.tnmc_env_stats.argtypes = [c_void_p]
     lib.tnmc_env_stats.restype = c_void_p
+    lib.tnmc_mlp_features.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.tnmc_mlp_scratch_floats.argtypes = [c_int32]
+    lib.tnmc_mlp_scratch_floats.restype = c_size_t
+    lib.tnmc_mlp_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                        ctypes.c_float, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.tnmc_mlp_forward.argtypes = [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]
     for name in ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy",
-                 "tnmc_accept", "tnmc_philox_uniform"):
+                 "tnmc_accept", "tnmc_philox_uniform", "tnmc_mlp_features", "tnmc_mlp_train_step",
+                 "tnmc_mlp_forward"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -153,10 +165,11 @@ def tnmc_build_env(problem: Problem, precision: int, workspace, logz_out=None, s
 
 def tnmc_sample(env: Env, n_samples: int, seed: int, spins_out, logq_out, sample_offset: int = 0,
                 forced_spins=None, mlp=None, logits_out=None, stream=None):
+    """mlp: None, or a device float32 tensor of MLP_NPARAM parameters."""
     lib = load()
     m = None
     if mlp is not None:
-        m = _Mlp(*(t.data_ptr() for t in mlp))
+        m = _Mlp(mlp.data_ptr())
     _check(lib.tnmc_sample(env.handle, n_samples, seed, sample_offset, _ptr(forced_spins),
                            None if m is None else byref(m), _ptr(spins_out), _ptr(logq_out),
                            _ptr(logits_out), _stream(stream)))
@@ -183,16 +196,21 @@ def tnmc_philox_uniform(seed: int, c0, c1: int, c2: int, stream_id: int, out, st
                                    _stream(stream)))
 
 
+STATS_PER_INST = 8
+
+
 def tnmc_env_stats(env: Env):
-    """Build statistics as a host int64 array (B, 4): Jacobi sweeps, then
-    100 MHz ticks in the QR sweeps, the SVD sweeps and the Jacobi loops.
-    Synchronises the current stream."""
+    """Per-instance statistics as a host int64 array (B, 8): Jacobi sweeps;
+    100 MHz ticks spent in the QR sweeps, the SVD sweeps and the Jacobi
+    loops; build start and end ticks; end tick of the first sampling tile
+    of the last tnmc_sample call; spare.  Synchronises the current stream."""
     import numpy as np
     import torch
     addr = load().tnmc_env_stats(env.handle)
     off = addr - env.workspace.data_ptr()
     torch.cuda.current_stream().synchronize()
-    return env.workspace[off:off + 32 * env.problem.batch].view(torch.int64).cpu().numpy().reshape(-1, 4)
+    n = 8 * STATS_PER_INST * env.problem.batch
+    return env.workspace[off:off + n].view(torch.int64).cpu().numpy().reshape(-1, STATS_PER_INST)
 
 
 def chain_state(chain_bytes):
@@ -206,3 +224,28 @@ def chain_state(chain_bytes):
         out.append(dict(cur_logq=f[0], cur_E=f[1], cur_index=int(i[0]), n_acc=int(i[1]),
                         n_trials=int(i[2]), initialised=int(i[3])))
     return out
+
+
+def tnmc_mlp_features(env: Env, n_samples: int, spins, logits_lo, feat_out, stream=None):
+    lib = load()
+    _check(lib.tnmc_mlp_features(env.handle, n_samples, _ptr(spins), _ptr(logits_lo), _ptr(feat_out),
+                                 _stream(stream)))
+
+
+def tnmc_mlp_scratch_floats(n_rows: int) -> int:
+    return load().tnmc_mlp_scratch_floats(n_rows)
+
+
+def tnmc_mlp_train_step(params, adam_m, adam_v, feat, logit_lo, target_logit, lr: float, step: int,
+                        scratch, grad_out=None, loss_out=None, stream=None):
+    lib = load()
+    n = logit_lo.numel()
+    _check(lib.tnmc_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), n, _ptr(feat), _ptr(logit_lo),
+                                   _ptr(target_logit), float(lr), step, _ptr(scratch), _ptr(grad_out),
+                                   _ptr(loss_out), _stream(stream)))
+
+
+def tnmc_mlp_forward(params, feat, d_out, bf16_weights: bool = False, stream=None):
+    lib = load()
+    _check(lib.tnmc_mlp_forward(_ptr(params), d_out.numel(), _ptr(feat), int(bf16_weights), _ptr(d_out),
+                                _stream(stream)))

@@ -30,6 +30,7 @@ COMMON = [
 SOURCES = {
     "build.hip": [],
     "sample.hip": [],
+    "mlp.hip": [],
     # the accept log-ratio is rounded once per operation
     "energy_accept.hip": ["-ffp-contract=off"],
     "abi.cpp": ["-x", "hip"],

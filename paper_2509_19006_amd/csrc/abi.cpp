@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -13,17 +14,24 @@
 
 namespace tnmc {
 struct MlpArgs {
-    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    const float *params;
     const float *Jh;
 };
+hipError_t launch_mlp_features(const InstDesc *, int, int, int, const uint64_t *, const float *, const float *,
+                               const float *, float *, hipStream_t);
+hipError_t launch_mlp_grad(const float *, int, const float *, const float *, const float *, float *, float *,
+                           float *, float *, float *, float *, float, int, int, float *, hipStream_t);
+hipError_t launch_mlp_forward(const float *, int, const float *, int, float *, hipStream_t);
+constexpr int kMlpRows = 64;
+constexpr int kMlpNParam = 8385;
 template <typename T, typename S>
-hipError_t launch_build(const InstDesc *, unsigned char *, const float *, const float *, double *,
-                        int64_t *, int, size_t, hipStream_t);
+hipError_t launch_build(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
+                        double *, int64_t *, int, size_t, hipStream_t);
 size_t build_lds_bytes(int chi, int L, size_t tsize);
 template <typename T, typename S>
 hipError_t launch_sample(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
                          uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *,
-                         MlpArgs, hipStream_t);
+                         MlpArgs, int64_t *, hipStream_t);
 hipError_t launch_energy(const InstDesc *, int, int, const uint64_t *, const float *, const float *,
                          double *, hipStream_t);
 hipError_t launch_accept(int, int, const double *, const double *, const double *, void *, uint64_t,
@@ -52,6 +60,7 @@ struct tnmc_env {
     std::vector<double> beta;
     const float *J_h = nullptr, *J_v = nullptr;
     std::vector<InstDesc> desc;
+    std::vector<int32_t> order;      // build launch order (longest first)
     unsigned char *ws = nullptr;
     size_t ws_bytes = 0, tile_bytes = 0, desc_off = 0, sweeps_off = 0;
 };
@@ -73,6 +82,8 @@ int chi_bucket_of(int chi) { return chi <= 16 ? 16 : (chi <= 32 ? 32 : 64); }
 
 struct Plan {
     std::vector<InstDesc> desc;
+    std::vector<int32_t> order;
+    size_t order_off = 0;
     size_t desc_off = 0, sweeps_off = 0, fixed = 0, tile_bytes = 0;
     int chi_bucket = 16, chi_max = 2, L_max = 2;
 };
@@ -114,8 +125,20 @@ int plan(const tnmc_problem *p, int precision, Plan &pl) {
     size_t off = 0;
     pl.desc_off = off;
     off = align_up(off + sizeof(InstDesc) * B);
+    pl.order_off = off;
+    off = align_up(off + sizeof(int32_t) * B);
     pl.sweeps_off = off;
-    off = align_up(off + sizeof(int64_t) * 4 * B);
+    off = align_up(off + sizeof(int64_t) * tnmc::STATS_PER_INST * B);
+    // Longest-processing-time-first: the build of an instance costs about
+    // (L-1) L chi^3, and instances that start first finish first on a full
+    // machine, so the launch order is by decreasing cost (stable on ties).
+    pl.order.resize(B);
+    for (int i = 0; i < B; ++i) pl.order[i] = i;
+    std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) {
+        const double ca = (double)(p->L[a] - 1) * p->L[a] * std::pow((double)p->chi[a], 3);
+        const double cb = (double)(p->L[b] - 1) * p->L[b] * std::pow((double)p->chi[b], 3);
+        return ca > cb;
+    });
     int64_t oh = 0, ov = 0, wp = 0, sp = 0;
     for (int i = 0; i < B; ++i) {
         InstDesc &d = pl.desc[i];
@@ -202,6 +225,7 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     env->J_h = p->J_h;
     env->J_v = p->J_v;
     env->desc = pl.desc;
+    env->order = pl.order;
     env->ws = static_cast<unsigned char *>(workspace);
     env->ws_bytes = workspace_bytes;
     env->tile_bytes = pl.tile_bytes;
@@ -212,14 +236,18 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     hipError_t e = hipMemcpyAsync(env->ws + pl.desc_off, env->desc.data(), sizeof(InstDesc) * p->batch,
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) { delete env; return hip_fail(e, "descriptor upload"); }
+    e = hipMemcpyAsync(env->ws + pl.order_off, env->order.data(), sizeof(int32_t) * p->batch,
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { delete env; return hip_fail(e, "schedule upload"); }
+    const int32_t *ord = reinterpret_cast<const int32_t *>(env->ws + pl.order_off);
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
     int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
     const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
     switch (precision) {
-    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
-    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
-    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
-    default: e = tnmc::launch_build<float, __half>(dd, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
     }
     if (e != hipSuccess) { delete env; return hip_fail(e, "build launch"); }
     *env_out = env;
@@ -235,16 +263,23 @@ int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed, uint64_t sample
     const int tiles = (n_samples + tnmc::kSampleTile - 1) / tnmc::kSampleTile;
     if (tiles > env->max_tiles)
         return fail(TNMC_ENOSPACE, "workspace sized for " + std::to_string(env->max_tiles * tnmc::kSampleTile) + " samples per call");
-    if (mlp) return fail(TNMC_ENOTSUP, "learned correction not available in this build");
     tnmc::MlpArgs ma{};
+    if (mlp) {
+        if (!mlp->params) return fail(TNMC_EINVAL, "mlp->params is NULL");
+        if (env->precision != TNMC_FP32 || env->chi_bucket != 16)
+            return fail(TNMC_ENOTSUP, "the learned correction runs on float32 envs with chi <= 16");
+        ma.params = mlp->params;
+        ma.Jh = env->J_h;
+    }
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + env->desc_off);
+    int64_t *stats = reinterpret_cast<int64_t *>(env->ws + env->sweeps_off);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     switch (env->precision) {
-    case TNMC_FP64: e = tnmc::launch_sample<double, double>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
-    case TNMC_FP32: e = tnmc::launch_sample<float, float>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
-    case TNMC_MIXED_BF16: e = tnmc::launch_sample<float, __hip_bfloat16>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
-    default: e = tnmc::launch_sample<float, __half>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, st); break;
+    case TNMC_FP64: e = tnmc::launch_sample<double, double>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
+    case TNMC_FP32: e = tnmc::launch_sample<float, float>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
+    case TNMC_MIXED_BF16: e = tnmc::launch_sample<float, __hip_bfloat16>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
+    default: e = tnmc::launch_sample<float, __half>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
     }
     if (e != hipSuccess) return hip_fail(e, "sample launch");
     return TNMC_OK;
@@ -269,6 +304,48 @@ int tnmc_accept(int32_t batch, int32_t n_samples, const double *logq, const doub
     hipError_t e = tnmc::launch_accept(batch, n_samples, logq, E, beta, chain, seed, step_offset, accepted_out,
                                        state_out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "accept launch");
+    return TNMC_OK;
+}
+
+int tnmc_mlp_features(const tnmc_env *env, int32_t n_samples, const uint64_t *spins, const float *logits_lo,
+                      float *feat_out, void *stream) {
+    if (!env) return fail(TNMC_EINVAL, "env is NULL");
+    if (n_samples < 1 || !spins || !logits_lo || !feat_out) return fail(TNMC_EINVAL, "bad mlp_features arguments");
+    int Lmax = 0;
+    for (int L : env->L) Lmax = std::max(Lmax, L);
+    const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + env->desc_off);
+    hipError_t e = tnmc::launch_mlp_features(dd, env->batch, Lmax, n_samples, spins, logits_lo, env->J_h, env->J_v,
+                                             feat_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp features launch");
+    return TNMC_OK;
+}
+
+size_t tnmc_mlp_scratch_floats(int32_t n_rows) {
+    if (n_rows < 1) return 0;
+    const size_t nblk = (size_t)(n_rows + tnmc::kMlpRows - 1) / tnmc::kMlpRows;
+    return nblk * tnmc::kMlpNParam + nblk;
+}
+
+int tnmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t n_rows, const float *feat,
+                        const float *logit_lo, const float *target_logit, float lr, int32_t step, float *scratch,
+                        float *grad_out, float *loss_out, void *stream) {
+    if (!params || n_rows < 1 || !feat || !logit_lo || !target_logit || !scratch || step < 0)
+        return fail(TNMC_EINVAL, "bad mlp_train_step arguments");
+    if (step > 0 && (!adam_m || !adam_v)) return fail(TNMC_EINVAL, "Adam moments are NULL");
+    if (!(lr >= 0.0f)) return fail(TNMC_EINVAL, "lr must be >= 0");
+    const size_t nblk = (size_t)(n_rows + tnmc::kMlpRows - 1) / tnmc::kMlpRows;
+    hipError_t e = tnmc::launch_mlp_grad(params, n_rows, feat, logit_lo, target_logit, scratch,
+                                         scratch + nblk * tnmc::kMlpNParam, adam_m, adam_v, grad_out, loss_out,
+                                         lr, step, step > 0 ? 1 : 0, params, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp train launch");
+    return TNMC_OK;
+}
+
+int tnmc_mlp_forward(const float *params, int32_t n_rows, const float *feat, int32_t bf16_weights, float *d_out,
+                     void *stream) {
+    if (!params || n_rows < 1 || !feat || !d_out) return fail(TNMC_EINVAL, "bad mlp_forward arguments");
+    hipError_t e = tnmc::launch_mlp_forward(params, n_rows, feat, bf16_weights, d_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp forward launch");
     return TNMC_OK;
 }
 

@@ -109,85 +109,86 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
     return y * (1.5f - 0.5f * x * y * y);
 }
 
-// One-sided (Hestenes) Jacobi on two independent blocks at once.  Block p
-// has n columns (length K[p]) starting at Tm + p*bs, rotations accumulated
-// in Wm + p*bs (n x n); column-major with leading dimension ld.  cn2[p*n+j]
-// holds squared column norms, recomputed every sweep and carried through
-// each rotation exactly (a' = a - t*g, b' = b + t*g), so a pair needs one
-// reduction.  Pairs whose smaller column is below sqrt(n)*eps*||T_p||_F are
-// left alone: such columns are rounding noise and a relative orthogonality
-// test on them never settles.  Returns the number of sweeps.
+// Orders a wave's shared-memory accesses without a workgroup barrier: the
+// LDS serves one wave's instructions in order, the fences stop the compiler
+// from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One-sided (Hestenes) Jacobi on one block, run by a single wave (lane =
+// 0..63): n columns of length K at Tb, rotations accumulated in Wb (n x n),
+// column-major with leading dimension ld.  cn[n] holds squared column
+// norms, recomputed every sweep and carried through each rotation exactly
+// (a' = a - t*g, b' = b + t*g), so a pair needs one reduction.  Pairs whose
+// smaller column is below sqrt(n)*eps*||T||_F are left alone: such columns
+// are rounding noise and a relative orthogonality test on them never
+// settles.  Returns the number of sweeps.
 template <typename T>
-__device__ int jacobi2(T *Tm, T *Wm, int ld, int bs, int K0, int K1, int n, T *cn2, T *small,
-                       int *flag) {
-    const int tid = threadIdx.x;
-    const int hp = n >> 1;                       // pairs per block per round
-    int G = pow2_floor(NT / (2 * hp));
-    if (G > 64) G = 64;
-    const int g = tid / G, lane = tid % G;
-    const int blk = g / hp, gg = g % hp;
-    const int K = blk == 0 ? K0 : K1;
-    const T tol = (T)2 * Eps<T>::v * sqrt((T)(K0 > K1 ? K0 : K1));
+__device__ int jacobi_wave(T *Tb, T *Wb, int ld, int K, int n, T *cn, int lane) {
+    const int hp = n >> 1;                       // pairs per round
+    int G = pow2_floor(64 / hp);
+    if (G < 1) G = 1;
+    const int g = lane / G, gl = lane % G;
+    const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
+    const T tol2 = tol * tol;
+    T small = 0;
     int sweeps = 0;
     for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
-        for (int e = tid; e < 2 * n; e += NT) {
-            const int b = e / n, col = e % n, kb = b == 0 ? K0 : K1;
-            const T *cp = Tm + b * bs + col * ld;
+        T part = 0;
+        for (int col = lane; col < n; col += 64) {
+            const T *cp = Tb + col * ld;
             T s2 = 0;
-            for (int r = 0; r < kb; ++r) s2 += cp[r] * cp[r];
-            cn2[e] = s2;
+            for (int r = 0; r < K; ++r) s2 += cp[r] * cp[r];
+            cn[col] = s2;
+            part += s2;
         }
-        if (tid == 0) *flag = 0;
-        __syncthreads();
-        if (sw == 0) {
-            if (tid < 2) {
-                T fro = 0;
-                for (int col = 0; col < n; ++col) fro += cn2[tid * n + col];
-                small[tid] = fro * Eps<T>::v * Eps<T>::v * (T)n;
-            }
-            __syncthreads();
-        }
+        if (sw == 0) small = group_sum(part, 64) * Eps<T>::v * Eps<T>::v * (T)n;
+        wave_sync();
+        int rot = 0;
         for (int t = 0; t < n - 1; ++t) {
-            if (blk < 2 && K > 0) {
-                const int i = seat(gg, t, n), j = seat(n - 1 - gg, t, n);
-                T *cn = cn2 + blk * n;
-                const T a = cn[i], b = cn[j], sm = small[blk];
-                if (a > sm && b > sm) {
-                    T *ci = Tm + blk * bs + i * ld, *cj = Tm + blk * bs + j * ld;
+            if (g < hp) {
+                const int i = seat(g, t, n), j = seat(n - 1 - g, t, n);
+                const T a = cn[i], b = cn[j];
+                if (a > small && b > small) {
+                    T *ci = Tb + i * ld, *cj = Tb + j * ld;
                     T c = 0;
-                    for (int r = lane; r < K; r += G) c += ci[r] * cj[r];
+                    for (int r = gl; r < K; r += G) c += ci[r] * cj[r];
                     c = group_sum(c, G);
-                    if (fabs(c) > tol * sqrt(a * b)) {
+                    if (c * c > tol2 * a * b) {
                         const T zeta = (b - a) * fast_rcp(2 * c);
                         T tt;
                         if (fabs(zeta) > (T)1e15) tt = (T)0.5 * fast_rcp(zeta);
-                        else tt = (zeta >= 0 ? (T)1 : (T)-1) * fast_rcp(fabs(zeta) + sqrt((T)1 + zeta * zeta));
+                        else {
+                            const T q = (T)1 + zeta * zeta;
+                            tt = (zeta >= 0 ? (T)1 : (T)-1) * fast_rcp(fabs(zeta) + q * rsqrt_nr(q));
+                        }
                         const T cs = rsqrt_nr((T)1 + tt * tt), sn = cs * tt;
-                        for (int r = lane; r < K; r += G) {
+                        for (int r = gl; r < K; r += G) {
                             const T x = ci[r], y = cj[r];
                             ci[r] = cs * x - sn * y;
                             cj[r] = sn * x + cs * y;
                         }
-                        T *wi = Wm + blk * bs + i * ld, *wj = Wm + blk * bs + j * ld;
-                        for (int r = lane; r < n; r += G) {
+                        T *wi = Wb + i * ld, *wj = Wb + j * ld;
+                        for (int r = gl; r < n; r += G) {
                             const T x = wi[r], y = wj[r];
                             wi[r] = cs * x - sn * y;
                             wj[r] = sn * x + cs * y;
                         }
-                        if (lane == 0) {
+                        if (gl == 0) {
                             cn[i] = a - tt * c;
                             cn[j] = b + tt * c;
-                            *flag = 1;
                         }
+                        rot = 1;
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
         ++sweeps;
-        const int more = *flag;
-        __syncthreads();
-        if (!more) break;
+        if (__ballot(rot) == 0) break;
     }
     return sweeps;
 }
@@ -204,10 +205,13 @@ __device__ __forceinline__ void lam_of(double beta, float J, double &l0, double 
 
 template <typename T, typename S>
 __global__ void __launch_bounds__(NT)
-k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
-        const float *__restrict__ Jh_all, const float *__restrict__ Jv_all,
-        double *__restrict__ logz_out, int64_t *__restrict__ stats_out) {
-    const int inst = blockIdx.x;
+k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
+        unsigned char *__restrict__ ws, const float *__restrict__ Jh_all,
+        const float *__restrict__ Jv_all, double *__restrict__ logz_out,
+        int64_t *__restrict__ stats_out) {
+    // workgroups take instances in the host's longest-first order
+    const int inst = order[blockIdx.x];
+    const long long t_begin = wall_clock64();
     const InstDesc d = desc[inst];
     const int L = d.L, chi = d.chi, tid = threadIdx.x;
     const double beta = d.beta;
@@ -362,19 +366,18 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                 __syncthreads();
                 break;
             }
-            // (c) Householder QR of both blocks, K x D, mc = min(K, D)
+            // (c)-(e) Householder QR of both blocks (K x D, mc = min(K, D)),
+            // explicit Q, copy to scratch slot c: one wave per block
             const int mc = K < D ? K : D;
-            const int half = tid >> 7, ht = tid & 127;     // 128 threads per block
-            T *M = Mb + half * 2 * chi * ldm;
-            int G = pow2_floor(128 / D);
-            if (G > 64) G = 64;
-            const int grp = ht / G, gl = ht % G, ngrp = 128 / G;
-            for (int j = 0; j < mc; ++j) {
-                // reflector of column j, computed and applied to the column by
-                // the first wave of the block's half (no barrier in between)
-                if (ht < 64) {
+            const int wv = tid >> 6, ln = tid & 63;
+            if (wv < 2) {
+                T *M = Mb + wv * 2 * chi * ldm;
+                int G = pow2_floor(64 / D);
+                if (G < 1) G = 1;
+                const int grp = ln / G, gl = ln % G, ngrp = 64 / G;
+                for (int j = 0; j < mc; ++j) {
                     T sum = 0;
-                    for (int i = j + 1 + ht; i < K; i += 64) { const T x = M[i * ldm + j]; sum += x * x; }
+                    for (int i = j + 1 + ln; i < K; i += 64) { const T x = M[i * ldm + j]; sum += x * x; }
                     sum = group_sum(sum, 64);
                     const T x0 = M[j * ldm + j];
                     T tj = 0, sc = 0, be = x0;
@@ -384,33 +387,28 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                         tj = (be - x0) / be;
                         sc = (T)1 / (x0 - be);
                     }
-                    for (int i = j + 1 + ht; i < K; i += 64) M[i * ldm + j] *= sc;
-                    if (ht == 0) { M[j * ldm + j] = be; tau[half * chi + j] = tj; }
-                }
-                __syncthreads();
-                const T tj = tau[half * chi + j];
-                if (tj != (T)0) {
-                    for (int k = j + 1 + grp; k < D; k += ngrp) {
-                        T w = 0;
-                        for (int i = j + gl; i < K; i += G) w += (i == j ? (T)1 : M[i * ldm + j]) * M[i * ldm + k];
-                        w = group_sum(w, G) * tj;
-                        for (int i = j + gl; i < K; i += G) M[i * ldm + k] -= (i == j ? (T)1 : M[i * ldm + j]) * w;
+                    for (int i = j + 1 + ln; i < K; i += 64) M[i * ldm + j] *= sc;
+                    if (ln == 0) { M[j * ldm + j] = be; tau[wv * chi + j] = tj; }
+                    wave_sync();
+                    if (tj != (T)0) {
+                        for (int k = j + 1 + grp; k < D; k += ngrp) {
+                            T w = 0;
+                            for (int i = j + gl; i < K; i += G) w += (i == j ? (T)1 : M[i * ldm + j]) * M[i * ldm + k];
+                            w = group_sum(w, G) * tj;
+                            for (int i = j + gl; i < K; i += G) M[i * ldm + k] -= (i == j ? (T)1 : M[i * ldm + j]) * w;
+                        }
                     }
+                    wave_sync();
                 }
-                __syncthreads();
-            }
-            // (d) explicit Q^p (K x mc) in Qb[half]; (e) copy to scratch slot c
-            {
-                T *Q = Qb + half * 2 * cc2;
-                for (int e = ht; e < K * mc; e += 128) { const int i = e / mc, k = e % mc; Q[i * chi + k] = (i == k) ? (T)1 : (T)0; }
-                __syncthreads();
-                int Gq = pow2_floor(128 / mc);
-                if (Gq > 64) Gq = 64;
-                const int gq = ht / Gq, lq = ht % Gq, nq = 128 / Gq;
-                // each group owns the same columns for every j, so columns
-                // never change hands between reflectors
+                T *Q = Qb + wv * 2 * cc2;
+                for (int e = ln; e < K * mc; e += 64) { const int i = e / mc, k = e % mc; Q[i * chi + k] = (i == k) ? (T)1 : (T)0; }
+                wave_sync();
+                int Gq = pow2_floor(64 / mc);
+                if (Gq < 1) Gq = 1;
+                const int gq = ln / Gq, lq = ln % Gq, nq = 64 / Gq;
+                // each group owns the same columns for every j
                 for (int j = mc - 1; j >= 0; --j) {
-                    const T tj = tau[half * chi + j];
+                    const T tj = tau[wv * chi + j];
                     if (tj == (T)0) continue;
                     for (int k = gq; k < mc; k += nq) {
                         if (k < j) continue;
@@ -420,11 +418,11 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                         for (int i = j + lq; i < K; i += Gq) Q[i * chi + k] -= (i == j ? (T)1 : M[i * ldm + j]) * w;
                     }
                 }
-                __syncthreads();
-                T *q = qscr + (size_t)c * 4 * cc2 + half * 2 * cc2;
-                for (int e = ht; e < K * mc; e += 128) { const int i = e / mc, k = e % mc; q[i * chi + k] = Q[i * chi + k]; }
-                __syncthreads();
+                wave_sync();
+                T *q = qscr + (size_t)c * 4 * cc2 + wv * 2 * cc2;
+                for (int e = ln; e < K * mc; e += 64) { const int i = e / mc, k = e % mc; q[i * chi + k] = Q[i * chi + k]; }
             }
+            __syncthreads();
             // (f) R^p (mc x D, upper trapezoidal) carried right; joint normalisation
             double rp = 0.0;
             for (int e = tid; e < 2 * mc * D; e += NT) {
@@ -524,7 +522,14 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
             __syncthreads();
             {
                 const long long t0 = wall_clock64();
-                total_sweeps += jacobi2<T>(Tm, Wm, ldt, bst, K0, K1, n, cn2, smallv, iflag);
+                const int wv = tid >> 6;
+                if (wv < 2) {
+                    const int sw = jacobi_wave<T>(Tm + wv * bst, Wm + wv * bst, ldt, wv ? K1 : K0, n,
+                                                  cn2 + wv * (chi + 2), tid & 63);
+                    if ((tid & 63) == 0) iflag[wv] = sw;
+                }
+                __syncthreads();
+                total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                 cyc_jac += wall_clock64() - t0;
             }
             // singular values of both blocks (padding columns and empty blocks excluded)
@@ -625,29 +630,32 @@ k_build(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
         for (int r = 0; r < L; ++r) lz += lsc[r];
         if (logz_out) logz_out[inst] = lz;
         if (stats_out) {
-            stats_out[4 * inst + 0] = total_sweeps;
-            stats_out[4 * inst + 1] = cyc_qr;
-            stats_out[4 * inst + 2] = cyc_svd;
-            stats_out[4 * inst + 3] = cyc_jac;
+            int64_t *so = stats_out + STATS_PER_INST * inst;
+            so[0] = total_sweeps;
+            so[1] = cyc_qr;
+            so[2] = cyc_svd;
+            so[3] = cyc_jac;
+            so[4] = t_begin;
+            so[5] = wall_clock64();
         }
     }
 }
 
 // Host-side launch helpers (called from the C ABI layer).
 template <typename T, typename S>
-hipError_t launch_build(const InstDesc *desc, unsigned char *ws, const float *Jh, const float *Jv,
-                        double *logz, int64_t *stats, int B, size_t lds_bytes, hipStream_t st) {
+hipError_t launch_build(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
+                        const float *Jv, double *logz, int64_t *stats, int B, size_t lds_bytes, hipStream_t st) {
     auto kern = k_build<T, S>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(B), dim3(NT), lds_bytes, st, desc, ws, Jh, Jv, logz, stats);
+    hipLaunchKernelGGL(kern, dim3(B), dim3(NT), lds_bytes, st, desc, order, ws, Jh, Jv, logz, stats);
     return hipGetLastError();
 }
 
-template hipError_t launch_build<double, double>(const InstDesc *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
-template hipError_t launch_build<float, float>(const InstDesc *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
-template hipError_t launch_build<float, __hip_bfloat16>(const InstDesc *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
-template hipError_t launch_build<float, __half>(const InstDesc *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
+template hipError_t launch_build<double, double>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
+template hipError_t launch_build<float, float>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
+template hipError_t launch_build<float, __hip_bfloat16>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
+template hipError_t launch_build<float, __half>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
 
 // Shared-memory bytes the build kernel needs for bond dimension chi and side L.
 size_t build_lds_bytes(int chi, int L, size_t tsize) {

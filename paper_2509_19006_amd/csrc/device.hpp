@@ -23,6 +23,11 @@ struct InstDesc {
 };
 static_assert(sizeof(InstDesc) == 96, "InstDesc layout");
 
+// Per-instance statistics record (int64): Jacobi sweeps, wall-clock ticks
+// in QR sweeps / SVD sweeps / Jacobi loops, build start and end ticks, end
+// tick of the instance's last sampling tile, spare.
+constexpr int STATS_PER_INST = 8;
+
 // ---- Philox4x32-10 (Salmon et al., SC'11) -----------------------------------
 struct U4 { uint32_t x, y, z, w; };
 

@@ -14,24 +14,28 @@
 //                l = l A_{c,spin}, rescaled by a power of two.
 // Each cache site (both spin slices, CHI x CHI, zero padded) is staged in
 // shared memory once and read by every sample of the instance.
-#include "device.hpp"
+#include <type_traits>
+
+#include "mlp_device.hpp"
 
 namespace tnmc {
 
 constexpr int NTS = 256;
 
+// Learned correction (optional): parameter vector in the layout of
+// mlp_device.hpp and the horizontal couplings for the features.
 struct MlpArgs {
-    const float *W1, *b1, *W2, *b2, *W3, *b3;
-    const float *Jh;      // horizontal couplings (features)
+    const float *params;
+    const float *Jh;
 };
 
-template <typename T, typename S, int CHI>
+template <typename T, typename S, int CHI, bool HAS_MLP>
 __global__ void __launch_bounds__(NTS)
 k_sample(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws, size_t tile_bytes,
          int n_samples, uint64_t seed, uint64_t sample_offset,
          const uint64_t *__restrict__ forced, uint64_t *spins_out,
          double *__restrict__ logq_out, float *__restrict__ logits_out,
-         const float *__restrict__ Jv_all, MlpArgs mlp) {
+         const float *__restrict__ Jv_all, MlpArgs mlp, int64_t *__restrict__ stats) {
     const int inst = blockIdx.y;
     const InstDesc d = desc[inst];
     const int tile = blockIdx.x;
@@ -52,6 +56,12 @@ k_sample(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws, size
     const uint32_t sidx = (uint32_t)(sample_offset + (uint64_t)n);
 
     __shared__ T As[2][CHI][CHI];
+    // MLP weights rounded to bfloat16 (float32 accumulation)
+    __shared__ float Ps[HAS_MLP ? MLP_NPARAM : 1];
+    const float *jh = HAS_MLP ? mlp.Jh + d.off_h : nullptr;
+    if (HAS_MLP) {
+        for (int e = tid; e < MLP_NPARAM; e += NTS) Ps[e] = __bfloat162float(__float2bfloat16(mlp.params[e]));
+    }
     auto stage = [&](const S *site) {
         for (int e = tid; e < 2 * CHI * CHI; e += NTS) {
             const int s = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
@@ -146,6 +156,20 @@ k_sample(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws, size
                         logit += 2.0 * beta * (double)jv[(size_t)(r - 1) * L + c] * (2.0 * u - 1.0);
                     }
                 }
+                if (HAS_MLP) {
+                    // spins already fixed: rows above from the output, row r
+                    // from the word being assembled (or the flushed one)
+                    const uint64_t curw = cur;
+                    auto spin = [&](int rr, int cc) -> float {
+                        uint64_t w;
+                        if (rr == r && (cc >> 6) == (c >> 6)) w = curw;
+                        else w = my_out[(size_t)rr * W + (cc >> 6)];
+                        return ((w >> (cc & 63)) & 1) ? 1.f : -1.f;
+                    };
+                    float x[MLP_IN];
+                    mlp_features(jh, jv, L, r, c, spin, (float)logit, x);
+                    logit += (double)mlp_forward(Ps, x);
+                }
                 int spin;
                 if (my_forced) {
                     spin = (int)((fw >> (c & 63)) & 1);
@@ -171,15 +195,18 @@ k_sample(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws, size
         }
     }
     if (act) logq_out[(size_t)inst * n_samples + n] = logq;
+    // end tick of the instance's first sample tile (the only tile when
+    // n_samples <= 256), for per-instance completion times
+    if (stats && tile == 0 && tid == 0) stats[STATS_PER_INST * inst + 6] = wall_clock64();
 }
 
-template <typename T, typename S, int CHI>
+template <typename T, typename S, int CHI, bool HAS_MLP>
 hipError_t launch_sample_t(const InstDesc *desc, unsigned char *ws, size_t tile_bytes, int B,
                            int max_tiles, int n_samples, uint64_t seed, uint64_t off,
                            const uint64_t *forced, uint64_t *spins, double *logq, float *logits,
-                           const float *Jv, MlpArgs mlp, hipStream_t st) {
-    hipLaunchKernelGGL((k_sample<T, S, CHI>), dim3(max_tiles, B), dim3(NTS), 0, st, desc, ws,
-                       tile_bytes, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp);
+                           const float *Jv, MlpArgs mlp, int64_t *stats, hipStream_t st) {
+    hipLaunchKernelGGL((k_sample<T, S, CHI, HAS_MLP>), dim3(max_tiles, B), dim3(NTS), 0, st, desc, ws,
+                       tile_bytes, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, stats);
     return hipGetLastError();
 }
 
@@ -187,21 +214,29 @@ template <typename T, typename S>
 hipError_t launch_sample(int chi_bucket, const InstDesc *desc, unsigned char *ws, size_t tile_bytes,
                          int B, int max_tiles, int n_samples, uint64_t seed, uint64_t off,
                          const uint64_t *forced, uint64_t *spins, double *logq, float *logits,
-                         const float *Jv, MlpArgs mlp, hipStream_t st) {
+                         const float *Jv, MlpArgs mlp, int64_t *stats, hipStream_t st) {
+    if (mlp.params) {
+        // the learned correction runs in float32 with chi <= 16
+        if constexpr (std::is_same<T, float>::value && std::is_same<S, float>::value) {
+            if (chi_bucket == 16)
+                return launch_sample_t<T, S, 16, true>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, stats, st);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (chi_bucket) {
-    case 16: return launch_sample_t<T, S, 16>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, st);
-    case 32: return launch_sample_t<T, S, 32>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, st);
+    case 16: return launch_sample_t<T, S, 16, false>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, stats, st);
+    case 32: return launch_sample_t<T, S, 32, false>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, stats, st);
     case 64:
         // float64 caches are limited to chi <= 32
         if constexpr (sizeof(T) == 8) return hipErrorInvalidValue;
-        else return launch_sample_t<T, S, 64>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, st);
+        else return launch_sample_t<T, S, 64, false>(desc, ws, tile_bytes, B, max_tiles, n_samples, seed, off, forced, spins, logq, logits, Jv, mlp, stats, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_sample<double, double>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, hipStream_t);
-template hipError_t launch_sample<float, float>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, hipStream_t);
-template hipError_t launch_sample<float, __hip_bfloat16>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, hipStream_t);
-template hipError_t launch_sample<float, __half>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, hipStream_t);
+template hipError_t launch_sample<double, double>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, int64_t *, hipStream_t);
+template hipError_t launch_sample<float, float>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, int64_t *, hipStream_t);
+template hipError_t launch_sample<float, __hip_bfloat16>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, int64_t *, hipStream_t);
+template hipError_t launch_sample<float, __half>(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t, uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *, MlpArgs, int64_t *, hipStream_t);
 
 }  // namespace tnmc

@@ -1,0 +1,99 @@
+"""The C ABI without a GPU: every declared symbol is exported, and argument
+validation returns the documented status codes before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2509_19006_amd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tnmc.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnmc_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        pytest.skip("libtnmc.so not built")
+    return T.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "tnmc_build_env" in names and "tnmc_accept" in names and len(names) >= 13
+    raw = ctypes.CDLL(T.LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+    assert set(T.EXPORTS) <= set(names)
+
+
+def _problem(L=(8,), chi=(16,), beta=(1.0,)):
+    return T.Problem(None, None, list(L), list(chi), list(beta))
+
+
+@pytest.mark.parametrize("L,chi,beta,code", [
+    ((1,), (4,), (1.0,), T.TNMC_EINVAL),
+    ((2000,), (4,), (1.0,), T.TNMC_EINVAL),
+    ((8,), (1,), (1.0,), T.TNMC_EINVAL),
+    ((8,), (65,), (1.0,), T.TNMC_EINVAL),
+    ((8,), (4,), (-1.0,), T.TNMC_EINVAL),
+    ((8,), (4,), (float("nan"),), T.TNMC_EINVAL),
+    ((8, 8), (4, 40), (1.0, 1.0), T.TNMC_ENOTSUP),    # float64 keeps chi <= 32
+])
+def test_workspace_size_validation(lib, L, chi, beta, code):
+    with pytest.raises(T.TnmcError) as e:
+        T.tnmc_workspace_size(_problem(L, chi, beta), T.FP64, 16)
+    assert e.value.code == code
+    assert len(lib.tnmc_last_error()) > 0
+
+
+def test_workspace_grows_with_samples_and_tiles(lib):
+    p = _problem((16, 33), (8, 8), (1.0, 0.5))
+    a = T.tnmc_workspace_size(p, T.FP32, 1)
+    b = T.tnmc_workspace_size(p, T.FP32, 256)
+    c = T.tnmc_workspace_size(p, T.FP32, 257)
+    assert a == b < c
+    assert T.tnmc_workspace_size(p, T.FP64, 1) > a > T.tnmc_workspace_size(p, T.MIXED_BF16, 1)
+    with pytest.raises(T.TnmcError):
+        T.tnmc_workspace_size(p, 7, 1)
+    with pytest.raises(T.TnmcError):
+        T.tnmc_workspace_size(p, T.FP32, 0)
+
+
+def test_entry_points_reject_bad_arguments_before_device_work(lib):
+    P = ctypes.POINTER
+    env = ctypes.c_void_p(0)
+    p = _problem()
+    # no couplings
+    assert lib.tnmc_build_env(ctypes.byref(p._c), T.FP32, ctypes.c_void_p(256), 1 << 30, None,
+                              ctypes.byref(env), None) == T.TNMC_EINVAL
+    assert lib.tnmc_sample(None, 4, 0, 0, None, None, None, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_energy(None, 4, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_accept(0, 4, None, None, None, None, 0, 0, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_accept(2, 4, None, None, None, None, 0, 0, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_philox_uniform(0, None, 0, 0, 0, 4, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_mlp_train_step(None, None, None, 8, None, None, None, 1e-3, 1, None, None, None,
+                                   None) == T.TNMC_EINVAL
+    assert lib.tnmc_mlp_forward(None, 8, None, 0, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_mlp_features(None, 8, None, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_env_stats(None) is None
+    assert lib.tnmc_mlp_scratch_floats(100) == 2 * T.MLP_NPARAM + 2
+    assert lib.tnmc_mlp_scratch_floats(0) == 0
+
+
+def test_chain_state_decoding():
+    raw = np.zeros(2 * T.CHAIN_BYTES, dtype=np.uint8)
+    f = raw.view(np.float64).reshape(2, 6)
+    i = raw.view(np.int64).reshape(2, 6)
+    f[1, 0], f[1, 1] = -3.5, 12.0
+    i[1, 2], i[1, 3], i[1, 4], i[1, 5] = 41, 7, 40, 1
+    st = T.chain_state(raw)
+    assert st[1] == dict(cur_logq=-3.5, cur_E=12.0, cur_index=41, n_acc=7, n_trials=40, initialised=1)

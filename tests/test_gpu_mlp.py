@@ -1,0 +1,164 @@
+"""GPU parity of the learned proposal correction against the float64 oracle,
+and what the trained network gains over the plain proposal.
+
+Tolerances: float32 kernels against float64 -- gradients within 2e-4 of
+the largest gradient entry, Adam parameters within 1e-6, forward within
+1e-4 (float32 weights) or 2e-2 relative with cosine >= 0.999 (bfloat16
+weights); features bit-exact (they are copies).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import bmps, mlp, sampler
+
+pytestmark = pytest.mark.gpu
+
+
+def _params_np(P):
+    v = P.detach().cpu().numpy().astype(np.float64)
+    return {"W1": v[0:4096].reshape(64, 64), "b1": v[4096:4160], "W2": v[4160:8256].reshape(64, 64),
+            "b2": v[8256:8320], "W3": v[8320:8384], "b3": v[8384:8385]}
+
+
+def _rand_params(torch, seed, out_scale=0.5):
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(-0.3, 0.3, 8385).astype(np.float32)
+    v[8320:8385] *= out_scale / 0.3
+    return torch.as_tensor(v).cuda()
+
+
+def _rows(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0, 1, (n, 64)).astype(np.float32)
+    x[:, 53:] = 0
+    lo = rng.normal(0, 3, n).astype(np.float32)
+    tg = (lo + rng.normal(0, 0.7, n)).astype(np.float32)
+    return x, lo, tg
+
+
+def test_gradient_and_adam_match_oracle(tnmc):
+    import torch
+    import tnmc_gpu as G
+    G.say("mlp gradient + adam, 1000 rows (16 groups, the last ragged)")
+    P = _rand_params(torch, 1)
+    x, lo, tg = _rows(1000, 2)
+    xt, lot, tgt = (torch.as_tensor(a).cuda() for a in (x, lo, tg))
+    scratch = torch.zeros(tnmc.tnmc_mlp_scratch_floats(1000), dtype=torch.float32, device="cuda")
+    grad = torch.zeros(8385, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    tnmc.tnmc_mlp_train_step(P, None, None, xt, lot, tgt, 0.0, 0, scratch, grad_out=grad, loss_out=loss)
+    torch.cuda.synchronize()
+    p = _params_np(P)
+    want = mlp.backward(p, x.astype(np.float64), lo.astype(np.float64), tg.astype(np.float64))
+    flat = np.concatenate([want[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    got = grad.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - flat)) < 2e-4 * np.max(np.abs(flat))
+    assert abs(loss.item() - mlp.loss(p, x.astype(np.float64), lo, tg)) < 1e-5
+    # one Adam step against the oracle's
+    m = torch.zeros(8385, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    tnmc.tnmc_mlp_train_step(P, m, v, xt, lot, tgt, 1e-3, 1, scratch)
+    torch.cuda.synchronize()
+    mo = {k: np.zeros_like(a) for k, a in p.items()}
+    vo = {k: np.zeros_like(a) for k, a in p.items()}
+    mlp.adam_step(p, want, mo, vo, 1, lr=1e-3)
+    newp = _params_np(P)
+    for k in p:
+        assert np.max(np.abs(newp[k] - p[k])) < 1e-6
+
+
+def test_forward_matches_oracle(tnmc):
+    import torch
+    P = _rand_params(torch, 3)
+    x, _, _ = _rows(700, 4)
+    d = torch.zeros(700, dtype=torch.float32, device="cuda")
+    tnmc.tnmc_mlp_forward(P, torch.as_tensor(x).cuda(), d)
+    torch.cuda.synchronize()
+    want, _ = mlp.forward(_params_np(P), x.astype(np.float64))
+    assert np.max(np.abs(d.cpu().numpy() - want)) < 1e-4
+    tnmc.tnmc_mlp_forward(P, torch.as_tensor(x).cuda(), d, bf16_weights=True)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - want) < 2e-2 * np.linalg.norm(want)
+    assert got @ want / (np.linalg.norm(got) * np.linalg.norm(want)) > 0.999
+
+
+def test_features_and_corrected_logits(tnmc):
+    """Features of GPU draws equal the oracle's; with a random network the
+    sampler's corrected logits equal TN logit + oracle MLP (bf16 weights)."""
+    import torch
+    import tnmc_gpu as G
+    L, chi, beta, n = 12, 8, 1.0, 24
+    Js = [workloads.instance(L, "gauss", 60, i) for i in range(2)]
+    G.say("mlp features + corrected logits, 2 x 12x12 chi 8")
+    run = G.Run(Js, chi, beta, tnmc.FP32, max_samples=n)
+    P = _rand_params(torch, 5, out_scale=0.2)
+    spins = torch.zeros(run.words(n), dtype=torch.int64, device="cuda")
+    logq = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    lg = torch.zeros(2 * n * L * L, dtype=torch.float32, device="cuda")
+    tnmc.tnmc_sample(run.env, n, 9, spins, logq, mlp=P, logits_out=lg)
+    # the TN logits of the same configurations (plain proposal, scored)
+    lg_tn = torch.zeros_like(lg)
+    tnmc.tnmc_sample(run.env, n, 9, spins.clone(), logq.clone(), forced_spins=spins, logits_out=lg_tn)
+    feat = torch.zeros((2 * n * L * L, 64), dtype=torch.float32, device="cuda")
+    tnmc.tnmc_mlp_features(run.env, n, spins, lg_tn, feat)
+    torch.cuda.synchronize()
+    sp = G.unpack(spins.cpu().numpy(), run.Ls, n)
+    f = feat.cpu().numpy().reshape(2, n, L, L, 64)
+    ltn = lg_tn.cpu().numpy().reshape(2, n, L, L)
+    got = lg.cpu().numpy().reshape(2, n, L, L)
+    pb = _params_np(P)
+    pb = {k: np.asarray(torch.as_tensor(a).to(torch.bfloat16).to(torch.float64)) for k, a in pb.items()}
+    for i, (jh, jv) in enumerate(Js):
+        for (r, c) in [(0, 0), (0, 5), (3, 0), (5, 7), (11, 11), (7, 1)]:
+            x = mlp.features(sp[i], jh, jv, ltn[i, :, r, c], r, c)
+            assert np.array_equal(f[i, :, r, c].astype(np.float64), x.astype(np.float32).astype(np.float64))
+            d, _ = mlp.forward(pb, x)
+            assert np.max(np.abs(got[i, :, r, c] - (ltn[i, :, r, c] + d))) < 2e-3
+
+
+def test_zero_network_is_the_plain_proposal(tnmc):
+    import torch
+    import tnmc_gpu as G
+    L, chi, n = 10, 8, 40
+    Js = [workloads.instance(L, "pmj", 61, i) for i in range(3)]
+    run = G.Run(Js, chi, 1.0, tnmc.FP32, max_samples=n)
+    P = _rand_params(torch, 6)
+    P[8320:8385] = 0.0          # output layer zero: d == 0 exactly
+    out = []
+    for m in (None, P):
+        spins = torch.zeros(run.words(n), dtype=torch.int64, device="cuda")
+        logq = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        tnmc.tnmc_sample(run.env, n, 17, spins, logq, mlp=m)
+        torch.cuda.synchronize()
+        out.append((spins.cpu().numpy(), logq.cpu().numpy()))
+    # identical draws; log q equal to float32 rounding (the variant with the
+    # network is a separate compilation whose float32 contraction order may
+    # differ by an ulp)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[0][1])) < 1e-6
+
+
+@pytest.mark.xfail(reason="training recipe under revision: first runs recovered ~2% of the loss "
+                          "and no acceptance gain", strict=False)
+def test_trained_network_raises_acceptance(tnmc):
+    """Train on high-chi conditionals of separately seeded disorders, then
+    compare acceptance of the low-chi proposal with and without the network
+    on held-out disorders (paired over disorders)."""
+    import torch
+    import tnmc_gpu as G
+    from paper_2509_19006_amd import learned
+    from scipy import stats
+    L, beta, lo_chi, hi_chi = 32, 1.0, 2, 16
+    train_J = [workloads.instance(L, "gauss", 70, i) for i in range(16)]
+    test_J = [workloads.instance(L, "gauss", 71, i) for i in range(16)]
+    G.say("learned correction: data (16 disorders x 32 draws at chi 16), training, evaluation")
+    feat, lo, tgt = learned.make_training_data(train_J, lo_chi, hi_chi, beta, 32, seed=3)
+    P, losses = learned.train(feat, lo, tgt, steps=400, batch=4096, lr=2e-3, seed=1, log=G.say)
+    assert losses[-1][1] < losses[0][1]
+    a0 = learned.acceptance(test_J, lo_chi, beta, 256, seed=11)
+    a1 = learned.acceptance(test_J, lo_chi, beta, 256, seed=11, mlp=P)
+    G.say(f"  acceptance plain {a0.mean():.3f} -> learned {a1.mean():.3f}")
+    assert a1.mean() > a0.mean()
+    assert stats.wilcoxon(a1 - a0, alternative="greater").pvalue < 0.01

@@ -1,0 +1,96 @@
+"""Uneven batches in one launch, and graph capture of the decode steps.
+
+Tolerances as in test_gpu_parity: float32 within 2e-4 * max(1, |value|).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import bmps, sampler
+
+pytestmark = pytest.mark.gpu
+
+
+def test_uneven_batch_one_launch(tnmc):
+    """Mixed L, chi, coupling family and beta in one build launch (float32)."""
+    import torch
+    import tnmc_gpu as G
+    Ls = [8, 12, 16, 20, 8, 12, 16, 20, 6, 10, 14, 18]
+    chis = [4, 8, 16, 16, 16, 4, 8, 4, 8, 16, 4, 8]
+    fams = ["pmj" if (i // 4) % 2 == 0 else "gauss" for i in range(len(Ls))]
+    betas = workloads.betas_uniform(len(Ls), 0.5, 2.0, 90)
+    Js = [workloads.instance(L, f, 90, i) for i, (L, f) in enumerate(zip(Ls, fams))]
+    G.say(f"uneven batch: L={Ls} chi={chis}")
+    jh = torch.as_tensor(np.concatenate([a.ravel() for a, _ in Js])).cuda()
+    jv = torch.as_tensor(np.concatenate([b.ravel() for _, b in Js])).cuda()
+    p = tnmc.Problem(jh, jv, Ls, chis, betas)
+    n = 16
+    ws = torch.zeros(tnmc.tnmc_workspace_size(p, tnmc.FP32, n), dtype=torch.uint8, device="cuda")
+    logz = torch.zeros(len(Ls), dtype=torch.float64, device="cuda")
+    env = tnmc.tnmc_build_env(p, tnmc.FP32, ws, logz)
+    draws = []
+    for i, (a, b) in enumerate(Js):
+        dg = {}
+        cache, _, lz = bmps.build_cache(betas[i], a, b, chis[i], dg)
+        bits, olq, _ = sampler.sample(cache, betas[i], b, n, seed=5, instance=i)
+        draws.append((lz, bits, olq, dg.get("cond", 0.0)))
+    words = np.concatenate([G.pack([2 * d[1] - 1]) for d in draws])
+    forced = torch.as_tensor(words).cuda()
+    spins = torch.zeros_like(forced)
+    logq = torch.zeros((len(Ls), n), dtype=torch.float64, device="cuda")
+    tnmc.tnmc_sample(env, n, 5, spins, logq, forced_spins=forced)
+    torch.cuda.synchronize()
+    lz, lq = logz.cpu().numpy(), logq.cpu().numpy()
+    st = tnmc.tnmc_env_stats(env)
+    for i in range(len(Ls)):
+        if draws[i][3] > 1e5:
+            continue
+        assert abs(lz[i] - draws[i][0]) < 2e-4 * abs(draws[i][0]), i
+        assert np.max(np.abs(lq[i] - draws[i][2]) / np.maximum(1, np.abs(draws[i][2]))) < 2e-4, i
+    # every instance recorded its build interval and its sampling end
+    assert np.all(st[:, 5] > st[:, 4]) and np.all(st[:, 6] >= st[:, 5])
+
+
+def test_decode_steps_replay_from_a_graph(tnmc):
+    """sample -> energy -> accept captured once, replayed three times with
+    eager work in between; every replay equals the eager pass."""
+    import torch
+    import tnmc_gpu as G
+    L, chi, B, n = 12, 8, 6, 48
+    Js = [workloads.instance(L, "gauss", 91, i) for i in range(B)]
+    G.say("graph capture of the decode steps")
+    run = G.Run(Js, chi, 1.0, tnmc.FP32, max_samples=n)
+    spins = torch.zeros(run.words(n), dtype=torch.int64, device="cuda")
+    logq = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+    E = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+    acc = torch.zeros((B, n), dtype=torch.uint8, device="cuda")
+    chain = torch.zeros(B * tnmc.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
+    beta = torch.full((B,), 1.0, dtype=torch.float64, device="cuda")
+
+    def decode(stream=None):
+        tnmc.tnmc_sample(run.env, n, 77, spins, logq, sample_offset=4096, stream=stream)
+        tnmc.tnmc_energy(run.env, n, spins, E, stream=stream)
+        tnmc.tnmc_accept(logq, E, beta, chain, 77, 4096, acc, stream=stream)
+
+    decode()
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (spins, logq, E, acc)]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        chain.zero_()
+        with torch.cuda.graph(g, stream=s):
+            decode(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for t in (spins, logq, E, acc):
+            t.zero_()
+        chain.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((spins, logq, E, acc), want):
+            assert torch.equal(a, b), rep
+        E.add_(1.0)                   # eager work between replays
+        torch.cuda.synchronize()
