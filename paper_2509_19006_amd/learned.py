@@ -125,3 +125,19 @@ def acceptance(Js, chi: int, beta: float, n_samples: int, seed: int, mlp=None):
     tnmc_accept(logq, E, torch.full((B,), float(beta), dtype=torch.float64, device="cuda"), chain, seed, 0, acc)
     st = chain_state(chain.cpu().numpy())
     return np.array([s["n_acc"] / max(1, s["n_trials"]) for s in st])
+
+
+def select(Js_val, chi: int, beta: float, mlp_params, n_samples: int = 256, seed: int = 11,
+           p_max: float = 0.05):
+    """Judge the learned proposal by acceptance on validation disorders.
+
+    Returns (chosen params or None, plain acceptances, learned acceptances):
+    the network is kept only if its acceptance beats the plain proposal's,
+    paired over disorders, with one-sided Wilcoxon p < p_max; otherwise the
+    plain TN proposal is the fallback (None)."""
+    from scipy import stats
+    a0 = acceptance(Js_val, chi, beta, n_samples, seed)
+    a1 = acceptance(Js_val, chi, beta, n_samples, seed, mlp=mlp_params)
+    d = a1 - a0
+    better = d.mean() > 0 and np.any(d != 0) and stats.wilcoxon(d, alternative="greater").pvalue < p_max
+    return (mlp_params if better else None), a0, a1
