@@ -230,7 +230,8 @@ int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
  * the QR sweeps, in the SVD sweeps, and inside the Jacobi iterations of the
  * SVD sweeps; the ticks at which the instance's build started and ended;
  * the tick at which the first sample tile of the last tnmc_sample call
- * ended (the only tile when n_samples <= 256); one spare slot.  The build
+ * ended (the only tile when n_samples <= 256); the ticks spent in the
+ * Householder factorisations (a part of the QR sweeps).  The build
  * processes instances in decreasing order of estimated cost (L-1) L chi^3.
  * NULL for a NULL env.                                                    */
 const int64_t *tnmc_env_stats(const tnmc_env *env);

@@ -203,7 +203,8 @@ def tnmc_env_stats(env: Env):
     """Per-instance statistics as a host int64 array (B, 8): Jacobi sweeps;
     100 MHz ticks spent in the QR sweeps, the SVD sweeps and the Jacobi
     loops; build start and end ticks; end tick of the first sampling tile
-    of the last tnmc_sample call; spare.  Synchronises the current stream."""
+    of the last tnmc_sample call; ticks in the Householder factorisations.
+    Synchronises the current stream."""
     import numpy as np
     import torch
     addr = load().tnmc_env_stats(env.handle)

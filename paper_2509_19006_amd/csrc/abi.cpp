@@ -26,7 +26,7 @@ constexpr int kMlpRows = 64;
 constexpr int kMlpNParam = 8385;
 template <typename T, typename S>
 hipError_t launch_build(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
-                        double *, int64_t *, int, size_t, hipStream_t);
+                        double *, int64_t *, int, int, size_t, hipStream_t);
 size_t build_lds_bytes(int chi, int L, size_t tsize);
 template <typename T, typename S>
 hipError_t launch_sample(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
@@ -244,10 +244,10 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
     const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
     switch (precision) {
-    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
-    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
-    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
-    default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, lds, st); break;
+    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
+    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
+    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
+    default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     }
     if (e != hipSuccess) { delete env; return hip_fail(e, "build launch"); }
     *env_out = env;

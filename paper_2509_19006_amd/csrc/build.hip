@@ -118,79 +118,326 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One-sided (Hestenes) Jacobi on one block, run by a single wave (lane =
-// 0..63): n columns of length K at Tb, rotations accumulated in Wb (n x n),
-// column-major with leading dimension ld.  cn[n] holds squared column
-// norms, recomputed every sweep and carried through each rotation exactly
-// (a' = a - t*g, b' = b + t*g), so a pair needs one reduction.  Pairs whose
-// smaller column is below sqrt(n)*eps*||T||_F are left alone: such columns
-// are rounding noise and a relative orthogonality test on them never
-// settles.  Returns the number of sweeps.
-template <typename T>
-__device__ int jacobi_wave(T *Tb, T *Wb, int ld, int K, int n, T *cn, int lane) {
-    const int hp = n >> 1;                       // pairs per round
-    int G = pow2_floor(64 / hp);
-    if (G < 1) G = 1;
-    const int g = lane / G, gl = lane % G;
+// Cross-lane read through the LDS permute crossbar: the value held by the
+// lane whose byte address is addr (lane * 4).
+template <typename T> __device__ __forceinline__ T bperm(int addr, T v);
+template <> __device__ __forceinline__ float bperm<float>(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+template <> __device__ __forceinline__ double bperm<double>(int addr, double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One-sided (Hestenes) Jacobi on one block, run by a single wave with the
+// block in registers.  The block has n columns (n even, n <= CHI) of length
+// K <= CHI at Tb, column-major with leading dimension ld; columns n..CHI-1
+// are treated as zero and never rotate.  The wave splits into CHI/2 lane
+// groups of G = 128/CHI lanes; group g holds one column pair (rows strided
+// over its lanes) of both the block and the accumulated rotation W.  Pairs
+// follow the round-robin ("circle") order: after every round the columns
+// move one seat along the ring (tops from the next group, bottoms from the
+// previous; group 0 keeps its top) through the LDS permute crossbar, so a
+// sweep of CHI-1 rounds meets every pair once and ends where it started.
+// Squared column norms are recomputed every sweep and carried through each
+// rotation exactly (a' = a - t*g, b' = b + t*g), so a pair needs one
+// reduction.  Pairs whose smaller column is below sqrt(n)*eps*||T||_F are
+// left alone: such columns are rounding noise and a relative orthogonality
+// test on them never settles.  On return the rotated block is back at Tb
+// and W (n x n, same leading dimension) at Wb.  Returns the sweep count.
+template <typename T, int CHI>
+__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane) {
+    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
+    int g = lane / G, gl = lane % G;
+    asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
+    const int ct = g, cb = CHI - 1 - g;          // columns held at the start of every sweep
+    T xt[RK], xb[RK], wt[RK], wb[RK];
+#pragma unroll
+    for (int i = 0; i < RK; ++i) {
+        const int row = gl + G * i;
+        xt[i] = (row < K && ct < n) ? Tb[ct * ld + row] : (T)0;
+        xb[i] = (row < K && cb < n) ? Tb[cb * ld + row] : (T)0;
+        wt[i] = (row == ct) ? (T)1 : (T)0;
+        wb[i] = (row == cb) ? (T)1 : (T)0;
+    }
+    const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
+    const bool first = (g == 0), last = (g == HP - 1);
     const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
     const T tol2 = tol * tol;
     T small = 0;
     int sweeps = 0;
     for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
-        T part = 0;
-        for (int col = lane; col < n; col += 64) {
-            const T *cp = Tb + col * ld;
-            T s2 = 0;
-            for (int r = 0; r < K; ++r) s2 += cp[r] * cp[r];
-            cn[col] = s2;
-            part += s2;
-        }
-        if (sw == 0) small = group_sum(part, 64) * Eps<T>::v * Eps<T>::v * (T)n;
-        wave_sync();
+        T a = 0, b = 0;
+#pragma unroll
+        for (int i = 0; i < RK; ++i) { a += xt[i] * xt[i]; b += xb[i] * xb[i]; }
+        if (sw == 0) small = group_sum(a + b, 64) * (T)(1.0 / G) * Eps<T>::v * Eps<T>::v * (T)n;
+        a = group_sum(a, G);
+        b = group_sum(b, G);
         int rot = 0;
-        for (int t = 0; t < n - 1; ++t) {
-            if (g < hp) {
-                const int i = seat(g, t, n), j = seat(n - 1 - g, t, n);
-                const T a = cn[i], b = cn[j];
-                if (a > small && b > small) {
-                    T *ci = Tb + i * ld, *cj = Tb + j * ld;
-                    T c = 0;
-                    for (int r = gl; r < K; r += G) c += ci[r] * cj[r];
-                    c = group_sum(c, G);
-                    if (c * c > tol2 * a * b) {
-                        const T zeta = (b - a) * fast_rcp(2 * c);
-                        T tt;
-                        if (fabs(zeta) > (T)1e15) tt = (T)0.5 * fast_rcp(zeta);
-                        else {
-                            const T q = (T)1 + zeta * zeta;
-                            tt = (zeta >= 0 ? (T)1 : (T)-1) * fast_rcp(fabs(zeta) + q * rsqrt_nr(q));
-                        }
-                        const T cs = rsqrt_nr((T)1 + tt * tt), sn = cs * tt;
-                        for (int r = gl; r < K; r += G) {
-                            const T x = ci[r], y = cj[r];
-                            ci[r] = cs * x - sn * y;
-                            cj[r] = sn * x + cs * y;
-                        }
-                        T *wi = Wb + i * ld, *wj = Wb + j * ld;
-                        for (int r = gl; r < n; r += G) {
-                            const T x = wi[r], y = wj[r];
-                            wi[r] = cs * x - sn * y;
-                            wj[r] = sn * x + cs * y;
-                        }
-                        if (gl == 0) {
-                            cn[i] = a - tt * c;
-                            cn[j] = b + tt * c;
-                        }
-                        rot = 1;
-                    }
+        for (int t = 0; t < CHI - 1; ++t) {
+            T c = 0;
+#pragma unroll
+            for (int i = 0; i < RK; ++i) c += xt[i] * xb[i];
+            c = group_sum(c, G);
+            T cs = 1, sn = 0, tt = 0;
+            if (a > small && b > small && c * c > tol2 * a * b) {
+                const T zeta = (b - a) * fast_rcp(2 * c);
+                if (fabs(zeta) > (T)1e15) tt = (T)0.5 * fast_rcp(zeta);
+                else {
+                    const T q = (T)1 + zeta * zeta;
+                    tt = (zeta >= 0 ? (T)1 : (T)-1) * fast_rcp(fabs(zeta) + q * rsqrt_nr(q));
+                }
+                cs = rsqrt_nr((T)1 + tt * tt);
+                sn = cs * tt;
+                rot = 1;
+            }
+#pragma unroll
+            for (int i = 0; i < RK; ++i) {
+                const T x = xt[i], y = xb[i];
+                xt[i] = cs * x - sn * y;
+                xb[i] = sn * x + cs * y;
+                const T u = wt[i], v = wb[i];
+                wt[i] = cs * u - sn * v;
+                wb[i] = sn * u + cs * v;
+            }
+            const T na = a - tt * c, nb = b + tt * c;
+            // circle move; permutes are issued in chunks of up to 8 rows
+            // before their selects, so the crossbar stays busy without
+            // holding a second copy of every row
+            const T An = bperm<T>(up, na), Bn = bperm<T>(dn, nb);
+            constexpr int CH = RK < 8 ? RK : 8;
+#pragma unroll
+            for (int i0 = 0; i0 < RK; i0 += CH) {
+                T At[CH], Bt[CH], Aw[CH], Bw[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    At[i] = bperm<T>(up, xt[i0 + i]);
+                    Bt[i] = bperm<T>(dn, xb[i0 + i]);
+                    Aw[i] = bperm<T>(up, wt[i0 + i]);
+                    Bw[i] = bperm<T>(dn, wb[i0 + i]);
+                }
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    xt[i0 + i] = first ? xt[i0 + i] : (last ? xb[i0 + i] : At[i]);
+                    xb[i0 + i] = first ? At[i] : Bt[i];
+                    wt[i0 + i] = first ? wt[i0 + i] : (last ? wb[i0 + i] : Aw[i]);
+                    wb[i0 + i] = first ? Aw[i] : Bw[i];
                 }
             }
-            wave_sync();
+            a = first ? na : (last ? nb : An);
+            b = first ? An : Bn;
         }
         ++sweeps;
         if (__ballot(rot) == 0) break;
     }
+#pragma unroll
+    for (int i = 0; i < RK; ++i) {
+        const int row = gl + G * i;
+        if (row < K) {
+            if (ct < n) Tb[ct * ld + row] = xt[i];
+            if (cb < n) Tb[cb * ld + row] = xb[i];
+        }
+        if (row < n) {
+            if (ct < n) Wb[ct * ld + row] = wt[i];
+            if (cb < n) Wb[cb * ld + row] = wb[i];
+        }
+    }
     return sweeps;
+}
+
+// The register Jacobi for the smallest compiled width that holds chi; MAXB
+// is the widest one compiled into this kernel (wider paths only cost
+// registers, so a kernel carries the ones its launch needs).
+template <typename T, int MAXB>
+__device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane) {
+    if (chi <= 16) return jacobi_reg<T, 16>(Tb, Wb, ld, K, n, lane);
+    if constexpr (MAXB <= 32) return jacobi_reg<T, 32>(Tb, Wb, ld, K, n, lane);
+    else {
+        if (chi <= 32) return jacobi_reg<T, 32>(Tb, Wb, ld, K, n, lane);
+        return jacobi_reg<T, 64>(Tb, Wb, ld, K, n, lane);
+    }
+}
+
+// One site of the QR sweep for both parity blocks, held in registers.
+// Block p belongs to waves 2p and 2p+1 (128 lanes); lane group grp (G =
+// 128/CHI lanes) owns column grp of M^p and each of its lanes RR = 2CHI/G
+// consecutive rows.  Shared memory (CHI-strided): C [CHI][CHI] (row a of the
+// old left bond, column b of the old right bond), R [2][CHI][CHI] (the
+// factor carried from the previous site, zero outside its trapezoid),
+// V [2][CHI][2CHI] (Householder vectors), tauv [2][CHI].
+//   M^p rows: sigma = 0 -> Rh^p C (m_p rows), sigma = 1 -> Rh^(1-p) C, where
+//   Rh^q scales column a of R^q by lam_h[(a's sector) ^ q]; at c = 0 the
+//   single row is C's first row.
+//   Householder QR (LAPACK's reflector convention): per column j the owner
+//   group publishes v_j and tau_j, every later column applies H_j.  The
+//   explicit Q (K x mc) goes to qdst ([2][2chi][chi], row-major, stride chi);
+//   R (mc x D, normalised jointly over both blocks) replaces the R array.
+// At the last site (D = 1) only block 0's single column is written to qdst
+// (the centre of the sweep) and nothing is factored.  Returns ln of the
+// joint norm (0 at the last site) and mc.
+template <typename T, int CHI>
+__device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, T lh0, T lh1,
+                          const T *C, T *R, T *V, T *tauv, T *qdst, int chi, double *red, int &mc_out,
+                          long long &cyc_hh) {
+    constexpr int G = 128 / CHI, RR = 2 * CHI / G;
+    const int tid = threadIdx.x, p = tid >> 7, lt = tid & 127;
+    int grp = lt / G, row0 = (lt % G) * RR;
+    // opaque to the optimiser: keeps the per-lane masks and addresses
+    // derived from these from being hoisted out of the row loop (they
+    // would stay live across the whole build)
+    asm volatile("" : "+v"(grp), "+v"(row0));
+    const int gl = row0 / RR;
+    const int mp = p ? m1 : m0;
+    T m[RR];
+    if (c == 0) {
+        const T x = (grp < D) ? C[grp] : (T)0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) m[r] = (row0 + r == 0) ? x : (T)0;
+    } else {
+        // M = sum_a R_q[k][a] C[a][grp] lam_h[...]: chunks of 4 columns of C
+        // against the rows' R entries, sectors accumulated apart
+        int roff[RR];
+        T accE[RR], accO[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int row = row0 + r;
+            const int q = (row < mp) ? p : 1 - p;
+            const int k = (row < K) ? ((row < mp) ? row : row - mp) : 0;
+            roff[r] = (q * CHI + k) * CHI;
+            accE[r] = 0;
+            accO[r] = 0;
+        }
+#pragma unroll 1
+        for (int a0 = 0; a0 < CHI; a0 += 4) {
+            T ce[4], co[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int a = a0 + i;
+                const T x = (a < Dp && grp < D) ? C[a * CHI + grp] : (T)0;
+                ce[i] = (a < pa0) ? x : (T)0;
+                co[i] = (a < pa0) ? (T)0 : x;
+            }
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const T *Rq = R + roff[r] + a0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const T rv = Rq[i];
+                    accE[r] += rv * ce[i];
+                    accO[r] += rv * co[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int row = row0 + r;
+            const bool q1 = (row < mp) ? (p == 1) : (p == 0);
+            const T v = q1 ? lh1 * accE[r] + lh0 * accO[r] : lh0 * accE[r] + lh1 * accO[r];
+            m[r] = (row < K) ? v : (T)0;
+        }
+    }
+    if (last) {
+        if (p == 0 && grp == 0) {
+#pragma unroll
+            for (int r = 0; r < RR; ++r) if (row0 + r < K) qdst[row0 + r] = m[r];
+        }
+        mc_out = 1;
+        return 0.0;
+    }
+    const long long th0 = wall_clock64();
+    const int mc = K < D ? K : D;
+    for (int j = 0; j < mc; ++j) {
+        T *vj = V + (p * CHI + j) * 2 * CHI;
+        if (grp == j) {
+            T s = 0, x0 = 0;
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const int row = row0 + r;
+                if (row > j) s += m[r] * m[r];
+                if (row == j) x0 = m[r];
+            }
+            s = group_sum(s, G);
+            x0 = group_sum(x0, G);
+            T tj = 0, sc = 0, be = x0;
+            if (s != (T)0) {
+                const T nr = sqrt(x0 * x0 + s);
+                be = x0 >= 0 ? -nr : nr;
+                tj = (be - x0) / be;
+                sc = (T)1 / (x0 - be);
+            }
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const int row = row0 + r;
+                vj[row] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
+                m[r] = row < j ? m[r] : (row == j ? be : (T)0);
+            }
+            if (gl == 0) tauv[p * CHI + j] = tj;
+        }
+        __syncthreads();
+        if (grp > j) {
+            const T tj = tauv[p * CHI + j];
+            if (tj != (T)0) {
+                T w = 0;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) w += vj[row0 + r] * m[r];
+                w = group_sum(w, G) * tj;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) m[r] -= vj[row0 + r] * w;
+            }
+        }
+    }
+    // explicit Q, backward accumulation: column k = grp
+    T qv[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) qv[r] = (row0 + r == grp) ? (T)1 : (T)0;
+    for (int j = mc - 1; j >= 0; --j) {
+        const T tj = tauv[p * CHI + j];
+        if (tj == (T)0 || grp < j) continue;
+        const T *vj = V + (p * CHI + j) * 2 * CHI;
+        T w = 0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) w += vj[row0 + r] * qv[r];
+        w = group_sum(w, G) * tj;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) qv[r] -= vj[row0 + r] * w;
+    }
+    if (grp < mc) {
+        T *qd = qdst + (size_t)p * 2 * chi * chi + grp;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) if (row0 + r < K) qd[(size_t)(row0 + r) * chi] = qv[r];
+    }
+    cyc_hh += wall_clock64() - th0;
+    // R^p (mc x D, upper trapezoidal), normalised jointly over both blocks
+    double part = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int row = row0 + r;
+        if (row < mc && row <= grp && grp < D) part += (double)m[r] * (double)m[r];
+    }
+    const double nu = sqrt(block_sum(part, red));
+    const T inv = (T)(1.0 / nu);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int row = row0 + r;
+        if (row < CHI) R[(p * CHI + row) * CHI + grp] = (row < mc && row <= grp && grp < D) ? m[r] * inv : (T)0;
+    }
+    mc_out = mc;
+    return log(nu);
+}
+
+template <typename T, int MAXB>
+__device__ double qr_site_any(int chi, int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, T lh0,
+                              T lh1, const T *C, T *R, T *V, T *tauv, T *qdst, double *red, int &mc,
+                              long long &cyc_hh) {
+    if (chi <= 16) return qr_site<T, 16>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    if constexpr (MAXB <= 32) {
+        return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    } else {
+        if (chi <= 32) return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        return qr_site<T, 64>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    }
 }
 
 // Eigenvalues (even, odd) of the normalised Boltzmann matrix of one bond:
@@ -203,7 +450,7 @@ __device__ __forceinline__ void lam_of(double beta, float J, double &l0, double 
     l1 = (J >= 0.0f) ? d : -d;
 }
 
-template <typename T, typename S>
+template <typename T, typename S, int MAXB>
 __global__ void __launch_bounds__(NT)
 k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
         unsigned char *__restrict__ ws, const float *__restrict__ Jh_all,
@@ -226,28 +473,26 @@ k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
     const int cc2 = chi * chi;
     const size_t site_sz = (size_t)2 * cc2;
     const size_t row_sz = (size_t)L * site_sz;
-    const int ldm = chi + 1;          // leading dim of M blocks
+    const int CB = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);   // compiled width holding chi
     const int ldt = chi + 1;          // leading dim of Tm / Wm blocks (column-major)
     const int bst = (chi + 1) * ldt;  // one Tm / Wm block
 
     // ---- shared memory layout (see build_lds_bytes) ----------------------
     extern __shared__ __align__(16) unsigned char smem[];
-    const int regA_sz = 4 * cc2 + 4 * chi * ldm;                   // QR phase
+    const int regA_sz = 7 * CB * CB;                               // QR phase
     const int regS_sz = 4 * bst + 2 * cc2;                         // SVD phase
     T *reg = reinterpret_cast<T *>(smem);
-    T *C = reg;                       // [chi][chi]
-    T *R = reg + cc2;                 // [2][chi][chi]
-    T *Qb = reg;                      // [2][2chi][chi]  (over C and R)
-    T *Mb = reg + 4 * cc2;            // [2][2chi][ldm]
+    T *C = reg;                       // [CB][CB]
+    T *R = reg + CB * CB;             // [2][CB][CB]
+    T *Vh = reg + 3 * CB * CB;        // [2][CB][2CB] Householder vectors
     T *Tm = reg;                      // [2][chi+1][ldt]
     T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
     T *X = reg + 4 * bst;             // [2][chi][chi]
     T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
-    T *tau = tail;                    // [2][chi]
-    T *nrm = tau + 2 * chi;           // [2][chi+2]
-    T *cn2 = nrm + 2 * (chi + 2);     // [2][chi+2]
-    T *smallv = cn2 + 2 * (chi + 2);  // [2]
-    double *red = reinterpret_cast<double *>(smallv + 2 + ((2 * chi + 2 * (chi + 2) * 2 + 2) & 1));
+    T *tau = tail;                    // [2][CB]
+    T *nrm = tau + 2 * CB;            // [2][chi+2]
+    double *red = reinterpret_cast<double *>(
+        (reinterpret_cast<uintptr_t>(nrm + 2 * (chi + 2)) + 7) & ~(uintptr_t)7);
     double *uvec = red + NT / 64;     // [2][64] row-0 contraction vector
     double *scal = uvec + 128;        // [8]
     int *colof = reinterpret_cast<int *>(scal + 8);   // [2chi+4] kept column of new bond slot
@@ -257,7 +502,7 @@ k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
     unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
 
     int total_sweeps = 0;
-    long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0;   // wall-clock ticks per phase
+    long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0, cyc_hh = 0;   // wall-clock ticks per phase
 
     // write one parity-basis site (from a generator) to the ping-pong buffer
     // and its spin-basis form to the cache
@@ -331,112 +576,20 @@ k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
             for (int e = tid; e < Dp * D; e += NT) {
                 const int a = e / D, b = e % D;
                 const int n = (a >= pa0) ^ (b >= pb0);
-                C[a * chi + b] = (T)(n ? lv1 : lv0) * os[n * cc2 + a * chi + b];
+                C[a * CB + b] = (T)(n ? lv1 : lv0) * os[n * cc2 + a * chi + b];
             }
+            double lh0 = 0.0, lh1 = 0.0;
+            if (c > 0) lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], lh0, lh1);
             __syncthreads();
-            // (b) M^p rows: sigma=0 -> Rh^p C (m_p rows), sigma=1 -> Rh^(1-p) C
-            const int nblk = (c == L - 1) ? 1 : 2;
-            if (c == 0) {
-                for (int e = tid; e < 2 * D; e += NT) {
-                    const int p = e / D, b = e % D;
-                    Mb[p * 2 * chi * ldm + b] = C[b];
-                }
-            } else {
-                double lh0, lh1;
-                lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], lh0, lh1);
-                for (int e = tid; e < nblk * K * D; e += NT) {
-                    const int p = e / (K * D), row = (e / D) % K, b = e % D;
-                    const int q = (row < (p == 0 ? m0 : m1)) ? p : 1 - p;      // R block of this row
-                    const int k = (q == p) ? row : row - (p == 0 ? m0 : m1);
-                    const T *Rq = R + q * cc2 + k * chi;
-                    T acc0 = 0, acc1 = 0;   // columns a in sector q (l = 0) / sector 1-q (l = 1)
-                    for (int a = k; a < Dp; ++a) {
-                        const T v = Rq[a] * C[a * chi + b];
-                        if ((a >= pa0) == (q == 1)) acc0 += v; else acc1 += v;
-                    }
-                    Mb[p * 2 * chi * ldm + row * ldm + b] = (T)lh0 * acc0 + (T)lh1 * acc1;
-                }
-            }
-            __syncthreads();
+            // (b)-(f) in registers: M^p, Householder QR, explicit Q to scratch
+            // slot c, normalised R carried right
+            int mc = 1;
+            ls += qr_site_any<T, MAXB>(chi, c, c == L - 1, K, D, Dp, pa0, m0, m1, (T)lh0, (T)lh1, C, R, Vh, tau,
+                                 qscr + (size_t)c * 4 * cc2, red, mc, cyc_hh);
             if (c == L - 1) {
-                // the center: single block, K x 1, kept for the SVD sweep
-                T *q = qscr + (size_t)c * 4 * cc2;
-                for (int e = tid; e < K; e += NT) q[e] = Mb[e * ldm];
                 if (tid == 0) { mq[2 * L] = 1; mq[2 * L + 1] = 0; }
                 __syncthreads();
                 break;
-            }
-            // (c)-(e) Householder QR of both blocks (K x D, mc = min(K, D)),
-            // explicit Q, copy to scratch slot c: one wave per block
-            const int mc = K < D ? K : D;
-            const int wv = tid >> 6, ln = tid & 63;
-            if (wv < 2) {
-                T *M = Mb + wv * 2 * chi * ldm;
-                int G = pow2_floor(64 / D);
-                if (G < 1) G = 1;
-                const int grp = ln / G, gl = ln % G, ngrp = 64 / G;
-                for (int j = 0; j < mc; ++j) {
-                    T sum = 0;
-                    for (int i = j + 1 + ln; i < K; i += 64) { const T x = M[i * ldm + j]; sum += x * x; }
-                    sum = group_sum(sum, 64);
-                    const T x0 = M[j * ldm + j];
-                    T tj = 0, sc = 0, be = x0;
-                    if (sum != (T)0) {
-                        const T nr = sqrt(x0 * x0 + sum);
-                        be = x0 >= 0 ? -nr : nr;
-                        tj = (be - x0) / be;
-                        sc = (T)1 / (x0 - be);
-                    }
-                    for (int i = j + 1 + ln; i < K; i += 64) M[i * ldm + j] *= sc;
-                    if (ln == 0) { M[j * ldm + j] = be; tau[wv * chi + j] = tj; }
-                    wave_sync();
-                    if (tj != (T)0) {
-                        for (int k = j + 1 + grp; k < D; k += ngrp) {
-                            T w = 0;
-                            for (int i = j + gl; i < K; i += G) w += (i == j ? (T)1 : M[i * ldm + j]) * M[i * ldm + k];
-                            w = group_sum(w, G) * tj;
-                            for (int i = j + gl; i < K; i += G) M[i * ldm + k] -= (i == j ? (T)1 : M[i * ldm + j]) * w;
-                        }
-                    }
-                    wave_sync();
-                }
-                T *Q = Qb + wv * 2 * cc2;
-                for (int e = ln; e < K * mc; e += 64) { const int i = e / mc, k = e % mc; Q[i * chi + k] = (i == k) ? (T)1 : (T)0; }
-                wave_sync();
-                int Gq = pow2_floor(64 / mc);
-                if (Gq < 1) Gq = 1;
-                const int gq = ln / Gq, lq = ln % Gq, nq = 64 / Gq;
-                // each group owns the same columns for every j
-                for (int j = mc - 1; j >= 0; --j) {
-                    const T tj = tau[wv * chi + j];
-                    if (tj == (T)0) continue;
-                    for (int k = gq; k < mc; k += nq) {
-                        if (k < j) continue;
-                        T w = 0;
-                        for (int i = j + lq; i < K; i += Gq) w += (i == j ? (T)1 : M[i * ldm + j]) * Q[i * chi + k];
-                        w = group_sum(w, Gq) * tj;
-                        for (int i = j + lq; i < K; i += Gq) Q[i * chi + k] -= (i == j ? (T)1 : M[i * ldm + j]) * w;
-                    }
-                }
-                wave_sync();
-                T *q = qscr + (size_t)c * 4 * cc2 + wv * 2 * cc2;
-                for (int e = ln; e < K * mc; e += 64) { const int i = e / mc, k = e % mc; q[i * chi + k] = Q[i * chi + k]; }
-            }
-            __syncthreads();
-            // (f) R^p (mc x D, upper trapezoidal) carried right; joint normalisation
-            double rp = 0.0;
-            for (int e = tid; e < 2 * mc * D; e += NT) {
-                const int p = e / (mc * D), j = (e / D) % mc, k = e % D;
-                const T v = (k >= j) ? Mb[p * 2 * chi * ldm + j * ldm + k] : (T)0;
-                R[p * cc2 + j * chi + k] = v;
-                rp += (double)v * (double)v;
-            }
-            const double nu = sqrt(block_sum(rp, red));
-            ls += log(nu);
-            const T inv = (T)(1.0 / nu);
-            for (int e = tid; e < 2 * mc * D; e += NT) {
-                const int p = e / (mc * D), j = (e / D) % mc, k = e % D;
-                R[p * cc2 + j * chi + k] *= inv;
             }
             if (tid == 0) { mq[2 * (c + 1)] = (unsigned char)mc; mq[2 * (c + 1) + 1] = (unsigned char)mc; }
             __syncthreads();
@@ -515,17 +668,12 @@ k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
                 }
             }
             __syncthreads();
-            for (int e = tid; e < 2 * n * n; e += NT) {
-                const int p = e / (n * n), col = (e / n) % n, row = e % n;
-                Wm[p * bst + col * ldt + row] = (row == col) ? (T)1 : (T)0;
-            }
-            __syncthreads();
             {
                 const long long t0 = wall_clock64();
                 const int wv = tid >> 6;
                 if (wv < 2) {
-                    const int sw = jacobi_wave<T>(Tm + wv * bst, Wm + wv * bst, ldt, wv ? K1 : K0, n,
-                                                  cn2 + wv * (chi + 2), tid & 63);
+                    const int sw = jacobi_block<T, MAXB>(Tm + wv * bst, Wm + wv * bst, ldt, wv ? K1 : K0, n, chi,
+                                                   tid & 63);
                     if ((tid & 63) == 0) iflag[wv] = sw;
                 }
                 __syncthreads();
@@ -637,32 +785,51 @@ k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
             so[3] = cyc_jac;
             so[4] = t_begin;
             so[5] = wall_clock64();
+            so[7] = cyc_hh;
         }
     }
 }
 
-// Host-side launch helpers (called from the C ABI layer).
-template <typename T, typename S>
-hipError_t launch_build(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
-                        const float *Jv, double *logz, int64_t *stats, int B, size_t lds_bytes, hipStream_t st) {
-    auto kern = k_build<T, S>;
+// Host-side launch helpers (called from the C ABI layer).  chi_max selects
+// the widest register path compiled into the kernel.
+template <typename T, typename S, int MAXB>
+hipError_t launch_build_w(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
+                          const float *Jv, double *logz, int64_t *stats, int B, size_t lds_bytes, hipStream_t st) {
+    auto kern = k_build<T, S, MAXB>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(B), dim3(NT), lds_bytes, st, desc, order, ws, Jh, Jv, logz, stats);
     return hipGetLastError();
 }
 
-template hipError_t launch_build<double, double>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
-template hipError_t launch_build<float, float>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
-template hipError_t launch_build<float, __hip_bfloat16>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
-template hipError_t launch_build<float, __half>(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *, double *, int64_t *, int, size_t, hipStream_t);
+template <typename T, typename S>
+hipError_t launch_build(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
+                        const float *Jv, double *logz, int64_t *stats, int B, int chi_max, size_t lds_bytes,
+                        hipStream_t st) {
+    if constexpr (sizeof(T) == 8) {
+        if (chi_max > 32) return hipErrorInvalidValue;
+        return launch_build_w<T, S, 32>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, st);
+    } else {
+        if (chi_max <= 32) return launch_build_w<T, S, 32>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, st);
+        return launch_build_w<T, S, 64>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, st);
+    }
+}
+
+#define TNMC_LB(T, S) template hipError_t launch_build<T, S>(const InstDesc *, const int32_t *, unsigned char *, \
+    const float *, const float *, double *, int64_t *, int, int, size_t, hipStream_t);
+TNMC_LB(double, double)
+TNMC_LB(float, float)
+TNMC_LB(float, __hip_bfloat16)
+TNMC_LB(float, __half)
+#undef TNMC_LB
 
 // Shared-memory bytes the build kernel needs for bond dimension chi and side L.
 size_t build_lds_bytes(int chi, int L, size_t tsize) {
-    const size_t regA = (size_t)4 * chi * chi + (size_t)4 * chi * (chi + 1);
+    const size_t cb = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);
+    const size_t regA = 7 * cb * cb;
     const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi;
     size_t elems = (regA > regS ? regA : regS);
-    elems += 2 * chi + 2 * (chi + 2) + 2 * (chi + 2) + 2 + 1;     // tau, nrm, cn2, small, align
+    elems += 2 * cb + 2 * (chi + 2);                          // tau, nrm
     size_t bytes = elems * tsize;
     bytes = (bytes + 7) & ~(size_t)7;
     bytes += (NT / 64 + 128 + 8) * sizeof(double);           // red, uvec, scal

@@ -25,7 +25,8 @@ static_assert(sizeof(InstDesc) == 96, "InstDesc layout");
 
 // Per-instance statistics record (int64): Jacobi sweeps, wall-clock ticks
 // in QR sweeps / SVD sweeps / Jacobi loops, build start and end ticks, end
-// tick of the instance's last sampling tile, spare.
+// tick of the instance's last sampling tile, ticks in the Householder
+// factorisations (part of the QR sweeps).
 constexpr int STATS_PER_INST = 8;
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) -----------------------------------
