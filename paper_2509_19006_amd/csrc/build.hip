@@ -131,39 +131,60 @@ template <> __device__ __forceinline__ double bperm<double>(int addr, double v) 
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Rotation that makes columns with squared norms a, b and inner product c
+// orthogonal: with d = b - a and e = 2c, tan = sign(d) e / (|d| + sqrt(d^2 +
+// e^2)) (the smaller root of Rutishauser's quadratic, free of overflow for
+// |d| >> |e|); identity (cs = 1, sn = t = 0) when the pair is orthogonal to
+// tolerance or either column is noise.  Returns whether it rotates.
+template <typename T>
+__device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, bool live, T &cs, T &sn, T &tt) {
+    const bool ok = live && a > small && b > small && c * c > tol2 * a * b;
+    const T d = b - a, e = c + c;
+    const T den = fabs(d) + sqrt(d * d + e * e);
+    const T t = (d >= 0 ? e : -e) * fast_rcp(ok ? den : (T)1);
+    const T c0 = rsqrt_nr((T)1 + t * t);
+    tt = ok ? t : (T)0;
+    cs = ok ? c0 : (T)1;
+    sn = ok ? c0 * t : (T)0;
+    return ok;
+}
+
 // One-sided (Hestenes) Jacobi on one block, run by a single wave with the
 // block in registers.  The block has n columns (n even, n <= CHI) of length
 // K <= CHI at Tb, column-major with leading dimension ld; columns n..CHI-1
-// are treated as zero and never rotate.  The wave splits into CHI/2 lane
-// groups of G = 128/CHI lanes; group g holds one column pair (rows strided
-// over its lanes) of both the block and the accumulated rotation W.  Pairs
-// follow the round-robin ("circle") order: after every round the columns
-// move one seat along the ring (tops from the next group, bottoms from the
-// previous; group 0 keeps its top) through the LDS permute crossbar, so a
-// sweep of CHI-1 rounds meets every pair once and ends where it started.
-// Squared column norms are recomputed every sweep and carried through each
-// rotation exactly (a' = a - t*g, b' = b + t*g), so a pair needs one
-// reduction.  Pairs whose smaller column is below sqrt(n)*eps*||T||_F are
-// left alone: such columns are rounding noise and a relative orthogonality
-// test on them never settles.  On return the rotated block is back at Tb
-// and W (n x n, same leading dimension) at Wb.  Returns the sweep count.
+// are treated as zero and never rotate.  Column pairs follow the odd-even
+// transposition order over CHI positions: even steps pair positions
+// (2g, 2g+1), odd steps (2g+1, 2g+2) with positions 0 and CHI-1 idle, and
+// every pair swaps positions after its step; CHI steps meet every pair once
+// and reverse the order.  The wave splits into CHI/2 lane groups of
+// G = 128/CHI lanes; group g holds the two columns of its pair (rows strided
+// over its lanes) for both the block and the accumulated rotation W.  Going
+// from an even to an odd step a group takes the second column of the next
+// group; going back, the first column of the previous group (the last group,
+// idle in odd steps, hands over its second): one move per column and step,
+// through the LDS permute crossbar.  Squared column norms are recomputed
+// every sweep and carried through each rotation exactly (a' = a - t*g,
+// b' = b + t*g), so a pair needs one reduction.  Pairs whose smaller column
+// is below sqrt(n)*eps*||T||_F are left alone: such columns are rounding
+// noise and a relative orthogonality test on them never settles.  On return
+// the rotated block is back at Tb and W (n x n, same leading dimension) at
+// Wb.  Returns the sweep count.
 template <typename T, int CHI>
 __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane) {
     constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
     int g = lane / G, gl = lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
-    const int ct = g, cb = CHI - 1 - g;          // columns held at the start of every sweep
-    T xt[RK], xb[RK], wt[RK], wb[RK];
+    T x[RK], y[RK], wx[RK], wy[RK];
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
-        xt[i] = (row < K && ct < n) ? Tb[ct * ld + row] : (T)0;
-        xb[i] = (row < K && cb < n) ? Tb[cb * ld + row] : (T)0;
-        wt[i] = (row == ct) ? (T)1 : (T)0;
-        wb[i] = (row == cb) ? (T)1 : (T)0;
+        x[i] = (row < K && 2 * g < n) ? Tb[(2 * g) * ld + row] : (T)0;
+        y[i] = (row < K && 2 * g + 1 < n) ? Tb[(2 * g + 1) * ld + row] : (T)0;
+        wx[i] = (row == 2 * g) ? (T)1 : (T)0;
+        wy[i] = (row == 2 * g + 1) ? (T)1 : (T)0;
     }
     const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
-    const bool first = (g == 0), last = (g == HP - 1);
+    const bool last = (g == HP - 1);
     const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
     const T tol2 = tol * tol;
     T small = 0;
@@ -171,77 +192,74 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane) {
     for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
         T a = 0, b = 0;
 #pragma unroll
-        for (int i = 0; i < RK; ++i) { a += xt[i] * xt[i]; b += xb[i] * xb[i]; }
+        for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
         if (sw == 0) small = group_sum(a + b, 64) * (T)(1.0 / G) * Eps<T>::v * Eps<T>::v * (T)n;
         a = group_sum(a, G);
         b = group_sum(b, G);
-        int rot = 0;
-        for (int t = 0; t < CHI - 1; ++t) {
-            T c = 0;
+        bool rot = false;
+        for (int t = 0; t < CHI; t += 2) {
 #pragma unroll
-            for (int i = 0; i < RK; ++i) c += xt[i] * xb[i];
-            c = group_sum(c, G);
-            T cs = 1, sn = 0, tt = 0;
-            if (a > small && b > small && c * c > tol2 * a * b) {
-                const T zeta = (b - a) * fast_rcp(2 * c);
-                if (fabs(zeta) > (T)1e15) tt = (T)0.5 * fast_rcp(zeta);
-                else {
-                    const T q = (T)1 + zeta * zeta;
-                    tt = (zeta >= 0 ? (T)1 : (T)-1) * fast_rcp(fabs(zeta) + q * rsqrt_nr(q));
+            for (int odd = 0; odd < 2; ++odd) {
+                T c0 = 0, c1 = 0;
+#pragma unroll
+                for (int i = 0; i < RK; i += 2) {
+                    c0 += x[i] * y[i];
+                    if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
                 }
-                cs = rsqrt_nr((T)1 + tt * tt);
-                sn = cs * tt;
-                rot = 1;
-            }
+                const T c = group_sum(c0 + c1, G);
+                T cs, sn, tt;
+                rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn, tt);
 #pragma unroll
-            for (int i = 0; i < RK; ++i) {
-                const T x = xt[i], y = xb[i];
-                xt[i] = cs * x - sn * y;
-                xb[i] = sn * x + cs * y;
-                const T u = wt[i], v = wb[i];
-                wt[i] = cs * u - sn * v;
-                wb[i] = sn * u + cs * v;
-            }
-            const T na = a - tt * c, nb = b + tt * c;
-            // circle move; permutes are issued in chunks of up to 8 rows
-            // before their selects, so the crossbar stays busy without
-            // holding a second copy of every row
-            const T An = bperm<T>(up, na), Bn = bperm<T>(dn, nb);
-            constexpr int CH = RK < 8 ? RK : 8;
-#pragma unroll
-            for (int i0 = 0; i0 < RK; i0 += CH) {
-                T At[CH], Bt[CH], Aw[CH], Bw[CH];
-#pragma unroll
-                for (int i = 0; i < CH; ++i) {
-                    At[i] = bperm<T>(up, xt[i0 + i]);
-                    Bt[i] = bperm<T>(dn, xb[i0 + i]);
-                    Aw[i] = bperm<T>(up, wt[i0 + i]);
-                    Bw[i] = bperm<T>(dn, wb[i0 + i]);
+                for (int i = 0; i < RK; ++i) {
+                    const T u = x[i], v = y[i];
+                    x[i] = cs * u - sn * v;
+                    y[i] = sn * u + cs * v;
+                    const T p = wx[i], q = wy[i];
+                    wx[i] = cs * p - sn * q;
+                    wy[i] = sn * p + cs * q;
                 }
+                a -= tt * c;
+                b += tt * c;
+                if (!odd) {
+                    // even -> odd layout: second column from the next group
 #pragma unroll
-                for (int i = 0; i < CH; ++i) {
-                    xt[i0 + i] = first ? xt[i0 + i] : (last ? xb[i0 + i] : At[i]);
-                    xb[i0 + i] = first ? At[i] : Bt[i];
-                    wt[i0 + i] = first ? wt[i0 + i] : (last ? wb[i0 + i] : Aw[i]);
-                    wb[i0 + i] = first ? Aw[i] : Bw[i];
+                    for (int i = 0; i < RK; ++i) { y[i] = bperm<T>(up, y[i]); wy[i] = bperm<T>(up, wy[i]); }
+                    b = bperm<T>(up, b);
+                } else {
+                    // odd -> even layout: first column from the previous
+                    // group; the idle last group keeps its first as second
+                    // and hands over its second
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) {
+                        const T sx = last ? y[i] : x[i], sw_ = last ? wy[i] : wx[i];
+                        const T nx = bperm<T>(dn, sx), nw = bperm<T>(dn, sw_);
+                        y[i] = last ? x[i] : y[i];
+                        wy[i] = last ? wx[i] : wy[i];
+                        x[i] = nx;
+                        wx[i] = nw;
+                    }
+                    const T na = bperm<T>(dn, last ? b : a);
+                    b = last ? a : b;
+                    a = na;
                 }
             }
-            a = first ? na : (last ? nb : An);
-            b = first ? An : Bn;
         }
         ++sweeps;
         if (__ballot(rot) == 0) break;
     }
+    // after an odd number of sweeps the positions are reversed
+    const bool rev = sweeps & 1;
+    const int cx = rev ? CHI - 1 - 2 * g : 2 * g, cy = rev ? CHI - 2 - 2 * g : 2 * g + 1;
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
         if (row < K) {
-            if (ct < n) Tb[ct * ld + row] = xt[i];
-            if (cb < n) Tb[cb * ld + row] = xb[i];
+            if (cx < n) Tb[cx * ld + row] = x[i];
+            if (cy < n) Tb[cy * ld + row] = y[i];
         }
         if (row < n) {
-            if (ct < n) Wb[ct * ld + row] = wt[i];
-            if (cb < n) Wb[cb * ld + row] = wb[i];
+            if (cx < n) Wb[cx * ld + row] = wx[i];
+            if (cy < n) Wb[cy * ld + row] = wy[i];
         }
     }
     return sweeps;
@@ -648,18 +666,18 @@ k_build(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
                 }
             } else {
                 const int mn0 = mq[2 * (c + 1)], mn1 = mq[2 * (c + 1) + 1];   // QR bond c|c+1 sectors
+                // idx fastest: neighbouring threads share rows of Q
                 for (int e = tid; e < 2 * n * chi; e += NT) {
-                    const int p = e / (n * chi), idx = (e / chi) % n, k = e % chi;
+                    const int p = e / (n * chi), k = (e / n) % chi, idx = e % n;
                     const int Kp = p ? K1 : K0;
                     T acc = 0;
                     if (k < Kp && idx < kr) {
                         const int dp = p ? r1 : r0;
-                        int qb, rowoff, xb, xc, mcq;
-                        if (idx < dp) { qb = p; rowoff = 0; xb = p; xc = idx; }
-                        else { qb = 1 - p; rowoff = qb ? K0 : K1; xb = 1 - p; xc = idx - dp; }
                         // rows of Q^qb: sigma=0 part (K_qb rows) first, then sigma=1 part
-                        rowoff = (idx < dp) ? 0 : (qb == 0 ? K0 : K1);
-                        mcq = xb ? mn1 : mn0;
+                        const bool s1 = idx >= dp;
+                        const int qb = s1 ? 1 - p : p, xb = qb, xc = s1 ? idx - dp : idx;
+                        const int rowoff = s1 ? (qb == 0 ? K0 : K1) : 0;
+                        const int mcq = xb ? mn1 : mn0;
                         const T *qr = q + qb * 2 * cc2 + (rowoff + k) * chi;
                         const T *xr = X + xb * cc2 + xc;
                         for (int j = 0; j < mcq; ++j) acc += qr[j] * xr[j * chi];
