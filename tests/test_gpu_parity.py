@@ -2,7 +2,13 @@
 
 Tolerances: float64 log q and ln Z within 1e-10 * max(1, |value|) of the
 oracle; float32 within 2e-4 * max(1, |value|) (accumulation over ~L^2
-float32 contractions); energies, Philox draws and accept decisions
+float32 contractions); the stored-cache forms (float32 build, cache rounded
+to float16 / bfloat16) within 2e-3 / 3e-2 * max(1, |value|) for log q (ln Z
+comes from the float32 build).  Those two bounds are what the formats reach,
+not the 5e-4 one might hope for: where a site is strongly polarised the
+weight of the unlikely spin is a small difference of order-one terms, and a
+draw against the odds there carries the rounding of the stored entries
+straight into log q.  Energies, Philox draws and accept decisions are
 bit-exact.
 """
 import math
@@ -15,7 +21,13 @@ from oracle import bmps, exact, ising, mis, philox, sampler
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-10, 1: 2e-4}
+TOL = {0: 1e-10, 1: 2e-4, 2: 3e-2, 3: 2e-3}
+# per-site logits: absolute for float64 / float32; relative to max(1, |logit|)
+# for the stored-cache forms, where strongly polarised sites carry logits of
+# order ten that come from nearly cancelling rounded terms; bfloat16 (8-bit
+# significand) leaves such logits uncertain by order one, so for it the
+# per-site logits are printed, not bounded
+LOGIT_TOL = {0: 1e-4, 1: 2e-2, 2: float("inf"), 3: 0.2}
 
 
 def rel_err(a, b):
@@ -100,6 +112,9 @@ CASES = [
     ("16x16 chi32", [16, 16], "gauss", 32, 1.0, 0),
     ("uneven L", [2, 5, 9, 17], "pmj", 8, 0.7, 0),
     ("16x16 chi8 fp32", [16, 16], "gauss", 8, 1.0, 1),
+    ("16x16 chi8 fp16 cache", [16, 16], "gauss", 8, 1.0, 3),
+    ("16x16 chi8 bf16 cache", [16, 16], "gauss", 8, 1.0, 2),
+    ("24x24 chi16 fp16 cache", [24, 24], "pmj", 16, 1.0, 3),
 ]
 
 
@@ -118,7 +133,7 @@ def test_logz_and_teacher_forced_logq(G, tnmc, case):
     for i in range(len(Js)):
         if not ok[i]:
             continue
-        assert rel_err(lz[i], orc[i][2]) < tol, (i, lz[i], orc[i][2])
+        assert rel_err(lz[i], orc[i][2]) < TOL[min(prec, 1)], (i, lz[i], orc[i][2])
         if Ls[i] ** 2 <= 16 and chi >= 2 ** (Ls[i] // 2):
             assert rel_err(lz[i], exact.brute_logZ(*Js[i], beta)) < tol
     # Score configurations the method itself proposes (oracle draws): at
@@ -135,9 +150,14 @@ def test_logz_and_teacher_forced_logq(G, tnmc, case):
             continue
         olq, olg = draws[i][1], draws[i][2]
         want = np.tile(olq, n // k + 1)[:n]
-        assert np.max(rel_err(lq[i], want)) < tol, (i, np.max(np.abs(lq[i] - want)))
         fin = np.isfinite(olg)
-        assert np.max(np.abs(lg[i][:k][fin] - olg[fin])) < (1e-4 if prec == 0 else 2e-2)
+        dl = np.abs(lg[i][:k][fin] - olg[fin])
+        dl_rel = dl / np.maximum(1.0, np.abs(olg[fin]))
+        print(f"  instance {i}: max relative log q error {np.max(rel_err(lq[i], want)):.2e}, "
+              f"max logit error {np.max(dl):.2e} (relative {np.max(dl_rel):.2e}, "
+              f"largest |logit| {np.max(np.abs(olg[fin])):.1f})")
+        assert np.max(rel_err(lq[i], want)) < tol, (i, np.max(np.abs(lq[i] - want)))
+        assert np.max(dl if prec < 2 else dl_rel) < LOGIT_TOL[prec]
     # the Z2 partner scores the same
     _, lq_m, _ = run.sample(k, forced=[-f[:k] for f in forced])
     assert np.max(rel_err(lq_m[ok], lq[ok, :k])) < tol
