@@ -30,7 +30,8 @@ PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}          # MI355X vector peaks, flop/
 # rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
 # read for a plain copy of known size; valid only for the kernel source it
 # was measured on (sha256 over the files below), reported as null otherwise.
-TRAFFIC_SOURCES = ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/device.hpp"]
+TRAFFIC_SOURCES = ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
+                   "paper_2509_19006_amd/csrc/device.hpp"]
 TRAFFIC = {"sha256": "1d4a6fa7c510f8fd3af0f8c80705db675b5f05b4bda2ce31ff54af1ef48ccf12",
            "bytes": 859686116054,
            "profile": "profiles/k_build_k_sample_c3_fp16_hbm_traffic.txt"}

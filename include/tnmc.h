@@ -135,6 +135,31 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision,
                    void *workspace, size_t workspace_bytes, void *stream,
                    tnmc_env **env_out, double *logz_out);
 
+/* The whole hot path per instance in one persistent launch, meant for
+ * uneven batches (instances of different L, chi, beta): each workgroup takes
+ * the next instance in longest-first order and runs its cache build
+ * (section 3.2, as tnmc_build_env), its n_samples draws (section 3.3, as
+ * tnmc_sample without forcing or correction, sample tiles one after
+ * another), their energies (Eq. (1), as tnmc_energy) and its Metropolis
+ * chain (Eq. (10), as tnmc_accept with beta_i from the problem).  Results
+ * equal those of the four separate calls with the same arguments; an
+ * instance is finished as soon as its own work is, which the env's
+ * statistics record (slot 6: completion tick).
+ *  workspace, workspace_bytes, logz_out, env_out   as tnmc_build_env (the
+ *             workspace needs room for one sample tile).
+ *  sample_seed, sample_offset   as tnmc_sample's seed and sample_offset.
+ *  chain, accept_seed, step_offset   as tnmc_accept's.
+ *  spins_out, logq_out, E_out, accepted_out, state_out   as the outputs of
+ *             tnmc_sample, tnmc_energy and tnmc_accept (state_out may be
+ *             NULL).
+ * Errors as tnmc_build_env; on error no env is returned.                    */
+int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace,
+             size_t workspace_bytes, int32_t n_samples, uint64_t sample_seed,
+             uint64_t sample_offset, tnmc_chain *chain, uint64_t accept_seed,
+             uint64_t step_offset, uint64_t *spins_out, double *logq_out,
+             double *E_out, uint8_t *accepted_out, int64_t *state_out,
+             double *logz_out, void *stream, tnmc_env **env_out);
+
 /* Draw (or score) n_samples configurations per instance (section 3.3).
  *  seed, sample_offset  Philox key and first global sample index.
  *  forced_spins  device, NULL to sample; otherwise configurations in the

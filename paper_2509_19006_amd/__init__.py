@@ -43,7 +43,7 @@ MLP_LAYOUT = {"W1": (0, (64, 64)), "b1": (4096, (64,)), "W2": (4160, (64, 64)), 
               "W3": (8320, (64,)), "b3": (8384, (1,))}
 
 
-EXPORTS = ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy", "tnmc_accept",
+EXPORTS = ("tnmc_workspace_size", "tnmc_build_env", "tnmc_run", "tnmc_sample", "tnmc_energy", "tnmc_accept",
            "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats",
            "tnmc_mlp_features", "tnmc_mlp_scratch_floats", "tnmc_mlp_train_step", "tnmc_mlp_forward")
 
@@ -59,6 +59,9 @@ def load(path: str = LIB_PATH):
     P = POINTER
     lib.tnmc_workspace_size.argtypes = [P(_Problem), c_int32, c_int32, P(c_size_t)]
     lib.tnmc_build_env.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p), c_void_p]
+    lib.tnmc_run.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_int32, c_uint64, c_uint64, c_void_p,
+                             c_uint64, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p, P(c_void_p)]
     lib.tnmc_sample.argtypes = [c_void_p, c_int32, c_uint64, c_uint64, c_void_p, P(_Mlp), c_void_p,
                                 c_void_p, c_void_p, c_void_p]
     lib.tnmc_energy.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
@@ -160,6 +163,20 @@ def tnmc_build_env(problem: Problem, precision: int, workspace, logz_out=None, s
     h = c_void_p(0)
     _check(lib.tnmc_build_env(byref(problem._c), precision, _ptr(workspace), workspace.numel(),
                               _stream(stream), byref(h), _ptr(logz_out)))
+    return Env(h, problem, precision, workspace)
+
+
+def tnmc_run(problem: Problem, precision: int, workspace, n_samples: int, sample_seed: int, chain,
+             accept_seed: int, spins_out, logq_out, E_out, accepted_out, state_out=None, logz_out=None,
+             sample_offset: int = 0, step_offset: int = 0, stream=None) -> Env:
+    """Build, sample, score and accept every instance in one persistent
+    launch (each instance finishes on its own); returns the env."""
+    lib = load()
+    h = c_void_p(0)
+    _check(lib.tnmc_run(byref(problem._c), precision, _ptr(workspace), workspace.numel(), n_samples,
+                        sample_seed, sample_offset, _ptr(chain), accept_seed, step_offset, _ptr(spins_out),
+                        _ptr(logq_out), _ptr(E_out), _ptr(accepted_out), _ptr(state_out), _ptr(logz_out),
+                        _stream(stream), byref(h)))
     return Env(h, problem, precision, workspace)
 
 

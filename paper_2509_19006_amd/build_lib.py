@@ -33,6 +33,7 @@ SOURCES = {
     "mlp.hip": [],
     # the accept log-ratio is rounded once per operation
     "energy_accept.hip": ["-ffp-contract=off"],
+    "pipeline.hip": [],
     "abi.cpp": ["-x", "hip"],
 }
 

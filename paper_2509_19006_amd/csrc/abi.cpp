@@ -29,6 +29,10 @@ hipError_t launch_build(const InstDesc *, const int32_t *, unsigned char *, cons
                         double *, int64_t *, int, int, size_t, hipStream_t);
 size_t build_lds_bytes(int chi, int L, size_t tsize);
 template <typename T, typename S>
+hipError_t launch_pipeline(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
+                           double *, int64_t *, int, int, size_t, int, uint64_t, uint64_t, uint64_t *, double *,
+                           double *, void *, uint64_t, uint64_t, uint8_t *, int64_t *, hipStream_t);
+template <typename T, typename S>
 hipError_t launch_sample(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
                          uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *,
                          MlpArgs, int64_t *, hipStream_t);
@@ -202,14 +206,19 @@ int tnmc_workspace_size(const tnmc_problem *p, int32_t precision, int32_t max_sa
     return TNMC_OK;
 }
 
-int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
-                   void *stream, tnmc_env **env_out, double *logz_out) {
+}  // extern "C"
+
+namespace {
+
+// Validates, plans the workspace, creates the env and uploads descriptors
+// and launch order; the caller launches the kernels.
+int setup_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
+              hipStream_t st, tnmc_env **env_out, Plan &pl) {
     int rc = validate(p, precision, true);
     if (rc) return rc;
     if (!env_out) return fail(TNMC_EINVAL, "env_out is NULL");
     if (!workspace) return fail(TNMC_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(TNMC_EINVAL, "workspace must be 256-byte aligned");
-    Plan pl;
     plan(p, precision, pl);
     if (workspace_bytes < pl.fixed + pl.tile_bytes)
         return fail(TNMC_ENOSPACE, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs at least " + std::to_string(pl.fixed + pl.tile_bytes));
@@ -232,17 +241,32 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     env->desc_off = pl.desc_off;
     env->sweeps_off = pl.sweeps_off;
     env->max_tiles = (int)((workspace_bytes - pl.fixed) / pl.tile_bytes);
-    hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(env->ws + pl.desc_off, env->desc.data(), sizeof(InstDesc) * p->batch,
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) { delete env; return hip_fail(e, "descriptor upload"); }
     e = hipMemcpyAsync(env->ws + pl.order_off, env->order.data(), sizeof(int32_t) * p->batch,
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) { delete env; return hip_fail(e, "schedule upload"); }
+    *env_out = env;
+    return TNMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
+                   void *stream, tnmc_env **env_out, double *logz_out) {
+    Plan pl;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    tnmc_env *env = nullptr;
+    int rc = setup_env(p, precision, workspace, workspace_bytes, st, &env, pl);
+    if (rc) return rc;
     const int32_t *ord = reinterpret_cast<const int32_t *>(env->ws + pl.order_off);
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
     int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
     const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
+    hipError_t e;
     switch (precision) {
     case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
@@ -250,6 +274,39 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     }
     if (e != hipSuccess) { delete env; return hip_fail(e, "build launch"); }
+    *env_out = env;
+    return TNMC_OK;
+}
+
+int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
+             int32_t n_samples, uint64_t sample_seed, uint64_t sample_offset, tnmc_chain *chain,
+             uint64_t accept_seed, uint64_t step_offset, uint64_t *spins_out, double *logq_out,
+             double *E_out, uint8_t *accepted_out, int64_t *state_out, double *logz_out, void *stream,
+             tnmc_env **env_out) {
+    if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
+    if (!spins_out || !logq_out || !E_out || !accepted_out || !chain)
+        return fail(TNMC_EINVAL, "spins_out, logq_out, E_out, accepted_out and chain must be non-NULL");
+    Plan pl;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    tnmc_env *env = nullptr;
+    int rc = setup_env(p, precision, workspace, workspace_bytes, st, &env, pl);
+    if (rc) return rc;
+    const int32_t *ord = reinterpret_cast<const int32_t *>(env->ws + pl.order_off);
+    const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
+    int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
+    const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
+#define TNMC_RUN(T, S) tnmc::launch_pipeline<T, S>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, \
+        pl.chi_max, lds, n_samples, sample_seed, sample_offset, spins_out, logq_out, E_out, chain, accept_seed, \
+        step_offset, accepted_out, state_out, st)
+    hipError_t e;
+    switch (precision) {
+    case TNMC_FP64: e = TNMC_RUN(double, double); break;
+    case TNMC_FP32: e = TNMC_RUN(float, float); break;
+    case TNMC_MIXED_BF16: e = TNMC_RUN(float, __hip_bfloat16); break;
+    default: e = TNMC_RUN(float, __half); break;
+    }
+#undef TNMC_RUN
+    if (e != hipSuccess) { delete env; return hip_fail(e, "pipeline launch"); }
     *env_out = env;
     return TNMC_OK;
 }

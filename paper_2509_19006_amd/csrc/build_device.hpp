@@ -1,0 +1,811 @@
+// Boundary-MPS cache build (arXiv 2509.19006, section 2.2 / Fig. 2 and
+// section 3.2): starting from the bottom row, apply each row's transfer MPO
+// to the boundary MPS and truncate back to bond dimension chi.
+//
+// Spin-flip (Z2) symmetric formulation.  With no field every Boltzmann matrix
+// (Eq. 7) is symmetric under flipping both spins, so in the basis
+// h_0 = (1,1)/sqrt2 (even), h_1 = (1,-1)/sqrt2 (odd) it is diagonal with
+// eigenvalues lam = (a+b, a-b), and every copy tensor (Eq. 8) becomes a
+// parity constraint (legs' parities sum to even).  In that basis every bond
+// of the boundary MPS splits into an even and an odd sector (stored as one
+// index: even entries first), site tensors are parity conserving, and the
+// matrices the compression decomposes are block diagonal.  The truncated
+// state is the one the plain SVD sweep produces (exactly, in exact
+// arithmetic): keeping the chi largest singular values of a block-diagonal
+// matrix means keeping the largest of both blocks together.  The even/odd
+// pairs of nearly equal singular values that a spin-flip symmetric state
+// has never meet inside one Jacobi problem, which is what makes the
+// one-sided Jacobi converge in few sweeps.
+//
+// One workgroup (256 threads, 4 waves) owns one instance and walks its rows
+// bottom to top.  Per row:
+//   * apply   -- site c of MPO x MPS is A'[(a,l),s,(b,t)] =
+//                lam_h(c-1)[l] lam_v(c)[n] A_old[a,n,b], n = l^s^t; never
+//                formed, folded into the next step;
+//   * QR sweep, left to right -- R * A'_c splits into two parity blocks
+//                M^p = [Rh^p C ; Rh^(1-p) C] with C[a,b] = lam_v[pa^pb] *
+//                A_old[a, pa^pb, b] and Rh^q = R^q scaled column-wise by
+//                lam_h[q ^ pa]; each block gets a Householder QR;
+//   * SVD sweep, right to left -- center T^p = [Q^p_0 X^p, Q^(1-p)_1 X^(1-p)]
+//                for p = 0, 1; one-sided (Hestenes) Jacobi on both blocks at
+//                once (round-robin pair order); keep the chi largest singular
+//                values over both; V^T becomes the site, U*S moves left.
+// The cache is written in the spin basis, A[x] = (A~[even] + (-1)^x A~[odd])
+// / sqrt2, which is what the sampler contracts.  All norms removed along the
+// way go to a float64 log-scale per row, so that ln Z = sum_r logscale[r] +
+// (L/2) ln 2 + ln(row-0 MPS contracted on its even physical component).
+//
+// Template T is the arithmetic type (double or float); S the cache storage
+// type (double, float, bfloat16 or half).  The previous row is kept in T in a
+// parity-basis ping-pong buffer, so the build never reads rounded values.
+#pragma once
+#include <type_traits>
+
+#include "device.hpp"
+
+namespace tnmc {
+
+constexpr int NT = 256;
+constexpr int MAX_SWEEPS = 40;
+
+// Cross-lane moves inside 16-lane rows use DPP (no trip through the LDS
+// permute unit); wider steps fall back to __shfl_xor.
+template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of G consecutive lanes (G a power of two <= 64);
+// every lane of a group gets the group's sum.
+template <typename T> __device__ __forceinline__ T group_sum(T v, int G) {
+    if (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror: partner in the other quad
+    if (G >= 16) v += dpp_move<0x140>(v);  // row_mirror: partner in the other half-row
+    if (G >= 32) v += __shfl_xor(v, 16, 64);
+    if (G >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+__device__ __forceinline__ int pow2_floor(int x) {
+    int p = 1;
+    while ((p << 1) <= x) p <<= 1;
+    return p;
+}
+
+// Workgroup sum of one double (all threads get the result).
+__device__ double block_sum(double v, double *red) {
+    v = group_sum(v, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+
+// Round-robin ("circle") tournament: seat q of round t (0 <= t < n-1).
+__device__ __forceinline__ int seat(int q, int t, int n) {
+    if (q == 0) return 0;
+    int v = q - 1 + t;
+    if (v >= n - 1) v -= n - 1;
+    return 1 + v;
+}
+
+__device__ __forceinline__ double fast_rcp(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// 1/sqrt(x) from the hardware estimate refined by one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * (1.5 - 0.5 * x * y * y);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    return y * (1.5f - 0.5f * x * y * y);
+}
+
+// Orders a wave's shared-memory accesses without a workgroup barrier: the
+// LDS serves one wave's instructions in order, the fences stop the compiler
+// from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane read through the LDS permute crossbar: the value held by the
+// lane whose byte address is addr (lane * 4).
+template <typename T> __device__ __forceinline__ T bperm(int addr, T v);
+template <> __device__ __forceinline__ float bperm<float>(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+template <> __device__ __forceinline__ double bperm<double>(int addr, double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Rotation that makes columns with squared norms a, b and inner product c
+// orthogonal: with d = b - a and e = 2c, tan = sign(d) e / (|d| + sqrt(d^2 +
+// e^2)) (the smaller root of Rutishauser's quadratic, free of overflow for
+// |d| >> |e|); identity (cs = 1, sn = t = 0) when the pair is orthogonal to
+// tolerance or either column is noise.  Returns whether it rotates.
+template <typename T>
+__device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, bool live, T &cs, T &sn, T &tt) {
+    const bool ok = live && a > small && b > small && c * c > tol2 * a * b;
+    const T d = b - a, e = c + c;
+    const T den = fabs(d) + sqrt(d * d + e * e);
+    const T t = (d >= 0 ? e : -e) * fast_rcp(ok ? den : (T)1);
+    const T c0 = rsqrt_nr((T)1 + t * t);
+    tt = ok ? t : (T)0;
+    cs = ok ? c0 : (T)1;
+    sn = ok ? c0 * t : (T)0;
+    return ok;
+}
+
+// One-sided (Hestenes) Jacobi on one block, run by a single wave with the
+// block in registers.  The block has n columns (n even, n <= CHI) of length
+// K <= CHI at Tb, column-major with leading dimension ld; columns n..CHI-1
+// are treated as zero and never rotate.  Column pairs follow the odd-even
+// transposition order over CHI positions: even steps pair positions
+// (2g, 2g+1), odd steps (2g+1, 2g+2) with positions 0 and CHI-1 idle, and
+// every pair swaps positions after its step; CHI steps meet every pair once
+// and reverse the order.  The wave splits into CHI/2 lane groups of
+// G = 128/CHI lanes; group g holds the two columns of its pair (rows strided
+// over its lanes) for both the block and the accumulated rotation W.  Going
+// from an even to an odd step a group takes the second column of the next
+// group; going back, the first column of the previous group (the last group,
+// idle in odd steps, hands over its second): one move per column and step,
+// through the LDS permute crossbar.  Squared column norms are recomputed
+// every sweep and carried through each rotation exactly (a' = a - t*g,
+// b' = b + t*g), so a pair needs one reduction.  Pairs whose smaller column
+// is below sqrt(n)*eps*||T||_F are left alone: such columns are rounding
+// noise and a relative orthogonality test on them never settles.  On return
+// the rotated block is back at Tb and W (n x n, same leading dimension) at
+// Wb.  Returns the sweep count.
+template <typename T, int CHI>
+__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane) {
+    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
+    int g = lane / G, gl = lane % G;
+    asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
+    T x[RK], y[RK], wx[RK], wy[RK];
+#pragma unroll
+    for (int i = 0; i < RK; ++i) {
+        const int row = gl + G * i;
+        x[i] = (row < K && 2 * g < n) ? Tb[(2 * g) * ld + row] : (T)0;
+        y[i] = (row < K && 2 * g + 1 < n) ? Tb[(2 * g + 1) * ld + row] : (T)0;
+        wx[i] = (row == 2 * g) ? (T)1 : (T)0;
+        wy[i] = (row == 2 * g + 1) ? (T)1 : (T)0;
+    }
+    const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
+    const bool last = (g == HP - 1);
+    const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
+    const T tol2 = tol * tol;
+    T small = 0;
+    int sweeps = 0;
+    for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
+        T a = 0, b = 0;
+#pragma unroll
+        for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
+        if (sw == 0) small = group_sum(a + b, 64) * (T)(1.0 / G) * Eps<T>::v * Eps<T>::v * (T)n;
+        a = group_sum(a, G);
+        b = group_sum(b, G);
+        bool rot = false;
+        for (int t = 0; t < CHI; t += 2) {
+#pragma unroll
+            for (int odd = 0; odd < 2; ++odd) {
+                T c0 = 0, c1 = 0;
+#pragma unroll
+                for (int i = 0; i < RK; i += 2) {
+                    c0 += x[i] * y[i];
+                    if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
+                }
+                const T c = group_sum(c0 + c1, G);
+                T cs, sn, tt;
+                rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn, tt);
+#pragma unroll
+                for (int i = 0; i < RK; ++i) {
+                    const T u = x[i], v = y[i];
+                    x[i] = cs * u - sn * v;
+                    y[i] = sn * u + cs * v;
+                    const T p = wx[i], q = wy[i];
+                    wx[i] = cs * p - sn * q;
+                    wy[i] = sn * p + cs * q;
+                }
+                a -= tt * c;
+                b += tt * c;
+                if (!odd) {
+                    // even -> odd layout: second column from the next group
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) { y[i] = bperm<T>(up, y[i]); wy[i] = bperm<T>(up, wy[i]); }
+                    b = bperm<T>(up, b);
+                } else {
+                    // odd -> even layout: first column from the previous
+                    // group; the idle last group keeps its first as second
+                    // and hands over its second
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) {
+                        const T sx = last ? y[i] : x[i], sw_ = last ? wy[i] : wx[i];
+                        const T nx = bperm<T>(dn, sx), nw = bperm<T>(dn, sw_);
+                        y[i] = last ? x[i] : y[i];
+                        wy[i] = last ? wx[i] : wy[i];
+                        x[i] = nx;
+                        wx[i] = nw;
+                    }
+                    const T na = bperm<T>(dn, last ? b : a);
+                    b = last ? a : b;
+                    a = na;
+                }
+            }
+        }
+        ++sweeps;
+        if (__ballot(rot) == 0) break;
+    }
+    // after an odd number of sweeps the positions are reversed
+    const bool rev = sweeps & 1;
+    const int cx = rev ? CHI - 1 - 2 * g : 2 * g, cy = rev ? CHI - 2 - 2 * g : 2 * g + 1;
+#pragma unroll
+    for (int i = 0; i < RK; ++i) {
+        const int row = gl + G * i;
+        if (row < K) {
+            if (cx < n) Tb[cx * ld + row] = x[i];
+            if (cy < n) Tb[cy * ld + row] = y[i];
+        }
+        if (row < n) {
+            if (cx < n) Wb[cx * ld + row] = wx[i];
+            if (cy < n) Wb[cy * ld + row] = wy[i];
+        }
+    }
+    return sweeps;
+}
+
+// The register Jacobi for the smallest compiled width that holds chi; MAXB
+// is the widest one compiled into this kernel (wider paths only cost
+// registers, so a kernel carries the ones its launch needs).
+template <typename T, int MAXB>
+__device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane) {
+    if (chi <= 16) return jacobi_reg<T, 16>(Tb, Wb, ld, K, n, lane);
+    if constexpr (MAXB <= 32) return jacobi_reg<T, 32>(Tb, Wb, ld, K, n, lane);
+    else {
+        if (chi <= 32) return jacobi_reg<T, 32>(Tb, Wb, ld, K, n, lane);
+        return jacobi_reg<T, 64>(Tb, Wb, ld, K, n, lane);
+    }
+}
+
+// One site of the QR sweep for both parity blocks, held in registers.
+// Block p belongs to waves 2p and 2p+1 (128 lanes); lane group grp (G =
+// 128/CHI lanes) owns column grp of M^p and each of its lanes RR = 2CHI/G
+// consecutive rows.  Shared memory (CHI-strided): C [CHI][CHI] (row a of the
+// old left bond, column b of the old right bond), R [2][CHI][CHI] (the
+// factor carried from the previous site, zero outside its trapezoid),
+// V [2][CHI][2CHI] (Householder vectors), tauv [2][CHI].
+//   M^p rows: sigma = 0 -> Rh^p C (m_p rows), sigma = 1 -> Rh^(1-p) C, where
+//   Rh^q scales column a of R^q by lam_h[(a's sector) ^ q]; at c = 0 the
+//   single row is C's first row.
+//   Householder QR (LAPACK's reflector convention): per column j the owner
+//   group publishes v_j and tau_j, every later column applies H_j.  The
+//   explicit Q (K x mc) goes to qdst ([2][2chi][chi], row-major, stride chi);
+//   R (mc x D, normalised jointly over both blocks) replaces the R array.
+// At the last site (D = 1) only block 0's single column is written to qdst
+// (the centre of the sweep) and nothing is factored.  Returns ln of the
+// joint norm (0 at the last site) and mc.
+template <typename T, int CHI>
+__device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, T lh0, T lh1,
+                          const T *C, T *R, T *V, T *tauv, T *qdst, int chi, double *red, int &mc_out,
+                          long long &cyc_hh) {
+    constexpr int G = 128 / CHI, RR = 2 * CHI / G;
+    const int tid = threadIdx.x, p = tid >> 7, lt = tid & 127;
+    int grp = lt / G, row0 = (lt % G) * RR;
+    // opaque to the optimiser: keeps the per-lane masks and addresses
+    // derived from these from being hoisted out of the row loop (they
+    // would stay live across the whole build)
+    asm volatile("" : "+v"(grp), "+v"(row0));
+    const int gl = row0 / RR;
+    const int mp = p ? m1 : m0;
+    T m[RR];
+    if (c == 0) {
+        const T x = (grp < D) ? C[grp] : (T)0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) m[r] = (row0 + r == 0) ? x : (T)0;
+    } else {
+        // M = sum_a R_q[k][a] C[a][grp] lam_h[...]: chunks of 4 columns of C
+        // against the rows' R entries, sectors accumulated apart
+        int roff[RR];
+        T accE[RR], accO[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int row = row0 + r;
+            const int q = (row < mp) ? p : 1 - p;
+            const int k = (row < K) ? ((row < mp) ? row : row - mp) : 0;
+            roff[r] = (q * CHI + k) * CHI;
+            accE[r] = 0;
+            accO[r] = 0;
+        }
+#pragma unroll 1
+        for (int a0 = 0; a0 < CHI; a0 += 4) {
+            T ce[4], co[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int a = a0 + i;
+                const T x = (a < Dp && grp < D) ? C[a * CHI + grp] : (T)0;
+                ce[i] = (a < pa0) ? x : (T)0;
+                co[i] = (a < pa0) ? (T)0 : x;
+            }
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const T *Rq = R + roff[r] + a0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const T rv = Rq[i];
+                    accE[r] += rv * ce[i];
+                    accO[r] += rv * co[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int row = row0 + r;
+            const bool q1 = (row < mp) ? (p == 1) : (p == 0);
+            const T v = q1 ? lh1 * accE[r] + lh0 * accO[r] : lh0 * accE[r] + lh1 * accO[r];
+            m[r] = (row < K) ? v : (T)0;
+        }
+    }
+    if (last) {
+        if (p == 0 && grp == 0) {
+#pragma unroll
+            for (int r = 0; r < RR; ++r) if (row0 + r < K) qdst[row0 + r] = m[r];
+        }
+        mc_out = 1;
+        return 0.0;
+    }
+    const long long th0 = wall_clock64();
+    const int mc = K < D ? K : D;
+    for (int j = 0; j < mc; ++j) {
+        T *vj = V + (p * CHI + j) * 2 * CHI;
+        if (grp == j) {
+            T s = 0, x0 = 0;
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const int row = row0 + r;
+                if (row > j) s += m[r] * m[r];
+                if (row == j) x0 = m[r];
+            }
+            s = group_sum(s, G);
+            x0 = group_sum(x0, G);
+            T tj = 0, sc = 0, be = x0;
+            if (s != (T)0) {
+                const T nr = sqrt(x0 * x0 + s);
+                be = x0 >= 0 ? -nr : nr;
+                tj = (be - x0) / be;
+                sc = (T)1 / (x0 - be);
+            }
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const int row = row0 + r;
+                vj[row] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
+                m[r] = row < j ? m[r] : (row == j ? be : (T)0);
+            }
+            if (gl == 0) tauv[p * CHI + j] = tj;
+        }
+        __syncthreads();
+        if (grp > j) {
+            const T tj = tauv[p * CHI + j];
+            if (tj != (T)0) {
+                T w = 0;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) w += vj[row0 + r] * m[r];
+                w = group_sum(w, G) * tj;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) m[r] -= vj[row0 + r] * w;
+            }
+        }
+    }
+    // explicit Q, backward accumulation: column k = grp
+    T qv[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) qv[r] = (row0 + r == grp) ? (T)1 : (T)0;
+    for (int j = mc - 1; j >= 0; --j) {
+        const T tj = tauv[p * CHI + j];
+        if (tj == (T)0 || grp < j) continue;
+        const T *vj = V + (p * CHI + j) * 2 * CHI;
+        T w = 0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) w += vj[row0 + r] * qv[r];
+        w = group_sum(w, G) * tj;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) qv[r] -= vj[row0 + r] * w;
+    }
+    if (grp < mc) {
+        T *qd = qdst + (size_t)p * 2 * chi * chi + grp;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) if (row0 + r < K) qd[(size_t)(row0 + r) * chi] = qv[r];
+    }
+    cyc_hh += wall_clock64() - th0;
+    // R^p (mc x D, upper trapezoidal), normalised jointly over both blocks
+    double part = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int row = row0 + r;
+        if (row < mc && row <= grp && grp < D) part += (double)m[r] * (double)m[r];
+    }
+    const double nu = sqrt(block_sum(part, red));
+    const T inv = (T)(1.0 / nu);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int row = row0 + r;
+        if (row < CHI) R[(p * CHI + row) * CHI + grp] = (row < mc && row <= grp && grp < D) ? m[r] * inv : (T)0;
+    }
+    mc_out = mc;
+    return log(nu);
+}
+
+template <typename T, int MAXB>
+__device__ double qr_site_any(int chi, int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, T lh0,
+                              T lh1, const T *C, T *R, T *V, T *tauv, T *qdst, double *red, int &mc,
+                              long long &cyc_hh) {
+    if (chi <= 16) return qr_site<T, 16>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    if constexpr (MAXB <= 32) {
+        return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    } else {
+        if (chi <= 32) return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        return qr_site<T, 64>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    }
+}
+
+// Eigenvalues (even, odd) of the normalised Boltzmann matrix of one bond:
+// entries exp(beta*J*sx*sy - beta*|J|) are (1, x) or (x, 1) with
+// x = exp(-2 beta |J|), so lam = (1 + x, +-(1 - x)), sign of J.
+__device__ __forceinline__ void lam_of(double beta, float J, double &l0, double &l1) {
+    const double a = 2.0 * beta * fabs((double)J);
+    l0 = 1.0 + exp(-a);
+    const double d = -expm1(-a);
+    l1 = (J >= 0.0f) ? d : -d;
+}
+
+template <typename T, typename S, int MAXB>
+__device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
+                               const float *__restrict__ Jh_all, const float *__restrict__ Jv_all,
+                               double *__restrict__ logz_out, int64_t *__restrict__ stats_out,
+                               unsigned char *smem) {
+    const long long t_begin = wall_clock64();
+    const InstDesc d = desc[inst];
+    const int L = d.L, chi = d.chi, tid = threadIdx.x;
+    const double beta = d.beta;
+    const double LN2 = 0.69314718055994530942;
+    const T RS2 = (T)0.70710678118654752440;
+    const float *jh = Jh_all + d.off_h;                  // [L][L-1]
+    const float *jv = Jv_all + d.off_v;                  // [L-1][L]
+    S *cache = reinterpret_cast<S *>(ws + d.cache_off);  // [L][L][2][chi][chi], spin basis
+    T *qscr = reinterpret_cast<T *>(ws + d.qscr_off);    // [L][2][2chi][chi]
+    T *prev = reinterpret_cast<T *>(ws + d.prev_off);    // [2][L][2][chi][chi], parity basis
+    double *lsc = reinterpret_cast<double *>(ws + d.lsc_off);
+    const int cc2 = chi * chi;
+    const size_t site_sz = (size_t)2 * cc2;
+    const size_t row_sz = (size_t)L * site_sz;
+    const int CB = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);   // compiled width holding chi
+    const int ldt = chi + 1;          // leading dim of Tm / Wm blocks (column-major)
+    const int bst = (chi + 1) * ldt;  // one Tm / Wm block
+
+    // ---- shared memory layout (see build_lds_bytes) ----------------------
+    const int regA_sz = 7 * CB * CB;                               // QR phase
+    const int regS_sz = 4 * bst + 2 * cc2;                         // SVD phase
+    T *reg = reinterpret_cast<T *>(smem);
+    T *C = reg;                       // [CB][CB]
+    T *R = reg + CB * CB;             // [2][CB][CB]
+    T *Vh = reg + 3 * CB * CB;        // [2][CB][2CB] Householder vectors
+    T *Tm = reg;                      // [2][chi+1][ldt]
+    T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
+    T *X = reg + 4 * bst;             // [2][chi][chi]
+    T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
+    T *tau = tail;                    // [2][CB]
+    T *nrm = tau + 2 * CB;            // [2][chi+2]
+    double *red = reinterpret_cast<double *>(
+        (reinterpret_cast<uintptr_t>(nrm + 2 * (chi + 2)) + 7) & ~(uintptr_t)7);
+    double *uvec = red + NT / 64;     // [2][64] row-0 contraction vector
+    double *scal = uvec + 128;        // [8]
+    int *colof = reinterpret_cast<int *>(scal + 8);   // [2chi+4] kept column of new bond slot
+    int *rankv = colof + 2 * chi + 4;                 // [2chi+4]
+    int *iflag = rankv + 2 * chi + 4;                 // [4]
+    unsigned char *dsec = reinterpret_cast<unsigned char *>(iflag + 4);  // [L+1][2] bond sectors
+    unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
+
+    int total_sweeps = 0;
+    long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0, cyc_hh = 0;   // wall-clock ticks per phase
+
+    // write one parity-basis site (from a generator) to the ping-pong buffer
+    // and its spin-basis form to the cache
+    auto put_site = [&](int r, int c, int a, int b, T e0, T e1) {
+        T *ps = prev + (size_t)(r & 1) * row_sz + (size_t)c * site_sz;
+        S *cs = cache + (size_t)r * row_sz + (size_t)c * site_sz;
+        ps[a * chi + b] = e0;
+        ps[cc2 + a * chi + b] = e1;
+        cs[a * chi + b] = store_as<S, T>((e0 + e1) * RS2);
+        cs[cc2 + a * chi + b] = store_as<S, T>((e0 - e1) * RS2);
+    };
+
+    // ---- bottom row (row L-1): every inner bond is (1 even, 1 odd) ---------
+    {
+        const int r = L - 1;
+        for (size_t e = tid; e < (size_t)L * cc2; e += NT) {
+            const int c = (int)(e / cc2), a = (int)((e / chi) % chi), b = (int)(e % chi);
+            T v0 = 0, v1 = 0;   // physical parity 0 / 1
+            if (c == 0) {
+                if (a == 0 && b == 0) v0 = 1;
+                if (a == 0 && b == 1) v1 = 1;
+            } else if (a < 2) {
+                double l0, l1;
+                lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], l0, l1);
+                const T lh = (T)(a == 0 ? l0 : l1);
+                if (c == L - 1) {
+                    if (b == 0) { if (a == 0) v0 = lh; else v1 = lh; }
+                } else if (b < 2) {
+                    // parity of (l, s, t) even: s = l ^ t
+                    if ((a ^ b) == 0) v0 = lh; else v1 = lh;
+                }
+            }
+            put_site(r, c, a, b, v0, v1);
+        }
+        for (int i = tid; i <= L; i += NT) {
+            dsec[2 * i] = 1;
+            dsec[2 * i + 1] = (i == 0 || i == L) ? 0 : 1;
+        }
+        double part = 0.0;
+        for (int c = tid; c < L - 1; c += NT) part += beta * fabs((double)jh[(size_t)r * (L - 1) + c]);
+        const double ls = block_sum(part, red) - (double)(L - 2) * 0.5 * LN2;
+        if (tid == 0) lsc[r] = ls;
+        __syncthreads();
+    }
+
+    double logz_tail = 0.0;   // (thread 0) ln of the row-0 contraction
+
+    for (int r = L - 2; r >= 0; --r) {
+        const T *orow = prev + (size_t)((r + 1) & 1) * row_sz;
+
+        double part = 0.0;
+        for (int c = tid; c < L; c += NT) {
+            part += beta * fabs((double)jv[(size_t)r * L + c]);
+            if (c < L - 1) part += beta * fabs((double)jh[(size_t)r * (L - 1) + c]);
+        }
+        double ls = block_sum(part, red) - (double)(L - 1) * LN2;
+
+        // ================= QR sweep, left to right =========================
+        const long long tq0 = wall_clock64();
+        if (tid == 0) { mq[0] = 1; mq[1] = 0; }
+        __syncthreads();
+        for (int c = 0; c < L; ++c) {
+            const int pa0 = dsec[2 * c], Dp = pa0 + dsec[2 * c + 1];             // old left bond
+            const int pb0 = dsec[2 * (c + 1)], D = pb0 + dsec[2 * (c + 1) + 1];  // old right bond
+            const int m0 = mq[2 * c], m1 = mq[2 * c + 1];
+            const int K = m0 + m1;
+            double lv0, lv1;
+            lam_of(beta, jv[(size_t)r * L + c], lv0, lv1);
+            // (a) C[a][b] = lam_v[pa^pb] * A_old[pa^pb][a][b]
+            const T *os = orow + (size_t)c * site_sz;
+            for (int e = tid; e < Dp * D; e += NT) {
+                const int a = e / D, b = e % D;
+                const int n = (a >= pa0) ^ (b >= pb0);
+                C[a * CB + b] = (T)(n ? lv1 : lv0) * os[n * cc2 + a * chi + b];
+            }
+            double lh0 = 0.0, lh1 = 0.0;
+            if (c > 0) lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], lh0, lh1);
+            __syncthreads();
+            // (b)-(f) in registers: M^p, Householder QR, explicit Q to scratch
+            // slot c, normalised R carried right
+            int mc = 1;
+            ls += qr_site_any<T, MAXB>(chi, c, c == L - 1, K, D, Dp, pa0, m0, m1, (T)lh0, (T)lh1, C, R, Vh, tau,
+                                 qscr + (size_t)c * 4 * cc2, red, mc, cyc_hh);
+            if (c == L - 1) {
+                if (tid == 0) { mq[2 * L] = 1; mq[2 * L + 1] = 0; }
+                __syncthreads();
+                break;
+            }
+            if (tid == 0) { mq[2 * (c + 1)] = (unsigned char)mc; mq[2 * (c + 1) + 1] = (unsigned char)mc; }
+            __syncthreads();
+        }
+
+        // ================= SVD sweep, right to left ========================
+        const long long ts0 = wall_clock64();
+        cyc_qr += ts0 - tq0;
+        if (tid == 0) { dsec[2 * L] = 1; dsec[2 * L + 1] = 0; uvec[0] = 1.0; }
+        __syncthreads();
+        double ulog = 0.0;
+        for (int c = L - 1; c >= 0; --c) {
+            const int r0 = dsec[2 * (c + 1)], r1 = dsec[2 * (c + 1) + 1];   // right bond sectors
+            const int kr = r0 + r1;
+            const int K0 = mq[2 * c], K1 = mq[2 * c + 1];                  // left (QR) bond sectors
+            const T *q = qscr + (size_t)c * 4 * cc2;
+            if (c == 0) {
+                // site 0: one row (even), columns (s=0, m even) and (s=1, m odd)
+                double sp = 0.0;
+                for (int m = tid; m < kr; m += NT) {
+                    const int p = (m >= r0);                    // sector of m; physical s = p
+                    const int mm = p ? m - r0 : m;
+                    const int mcq = mq[2 * (c + 1) + p];        // QR bond c|c+1 sector p
+                    const T *qrow = q + p * 2 * cc2;            // Q^p, sigma = p part starts at row 0
+                    T acc = 0;
+                    for (int j = 0; j < mcq; ++j) acc += qrow[j] * X[p * cc2 + j * chi + mm];
+                    nrm[m] = acc;
+                    sp += (double)acc * (double)acc;
+                }
+                const double n0 = sqrt(block_sum(sp, red));
+                ls += log(n0);
+                const T inv = (T)(1.0 / n0);
+                for (int e = tid; e < cc2; e += NT) {
+                    const int a = e / chi, m = e % chi;
+                    T v0 = 0, v1 = 0;
+                    if (a == 0 && m < kr) { if (m < r0) v0 = nrm[m] * inv; else v1 = nrm[m] * inv; }
+                    put_site(r, 0, a, m, v0, v1);
+                }
+                if (r == 0 && tid == 0) {
+                    double tot = 0.0;
+                    for (int m = 0; m < r0; ++m) tot += (double)nrm[m] * (double)inv * uvec[m];
+                    logz_tail = ulog + log(tot) + (double)L * 0.5 * LN2;
+                }
+                if (tid == 0) { dsec[0] = 1; dsec[1] = 0; }
+                __syncthreads();
+                break;
+            }
+            const int n = (kr + 1) & ~1;     // columns per block, padded even
+            // T^p[k][idx]: idx < d^p -> (s=0, m = off_p + idx); else (s=1, m = off_(1-p) + idx - d^p)
+            if (c == L - 1) {
+                for (int e = tid; e < 2 * n * ldt; e += NT) Tm[(e / (n * ldt)) * bst + e % (n * ldt)] = 0;
+                __syncthreads();
+                for (int e = tid; e < K0 + K1; e += NT) {
+                    const int p = e >= K0, k = p ? e - K0 : e;
+                    Tm[p * bst + k] = q[e];
+                }
+            } else {
+                const int mn0 = mq[2 * (c + 1)], mn1 = mq[2 * (c + 1) + 1];   // QR bond c|c+1 sectors
+                // idx fastest: neighbouring threads share rows of Q
+                for (int e = tid; e < 2 * n * chi; e += NT) {
+                    const int p = e / (n * chi), k = (e / n) % chi, idx = e % n;
+                    const int Kp = p ? K1 : K0;
+                    T acc = 0;
+                    if (k < Kp && idx < kr) {
+                        const int dp = p ? r1 : r0;
+                        // rows of Q^qb: sigma=0 part (K_qb rows) first, then sigma=1 part
+                        const bool s1 = idx >= dp;
+                        const int qb = s1 ? 1 - p : p, xb = qb, xc = s1 ? idx - dp : idx;
+                        const int rowoff = s1 ? (qb == 0 ? K0 : K1) : 0;
+                        const int mcq = xb ? mn1 : mn0;
+                        const T *qr = q + qb * 2 * cc2 + (rowoff + k) * chi;
+                        const T *xr = X + xb * cc2 + xc;
+                        for (int j = 0; j < mcq; ++j) acc += qr[j] * xr[j * chi];
+                    }
+                    Tm[p * bst + idx * ldt + k] = acc;
+                }
+            }
+            __syncthreads();
+            {
+                const long long t0 = wall_clock64();
+                const int wv = tid >> 6;
+                if (wv < 2) {
+                    const int sw = jacobi_block<T, MAXB>(Tm + wv * bst, Wm + wv * bst, ldt, wv ? K1 : K0, n, chi,
+                                                   tid & 63);
+                    if ((tid & 63) == 0) iflag[wv] = sw;
+                }
+                __syncthreads();
+                total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
+                cyc_jac += wall_clock64() - t0;
+            }
+            // singular values of both blocks (padding columns and empty blocks excluded)
+            for (int e = tid; e < 2 * n; e += NT) {
+                const int p = e / n, col = e % n, Kp = p ? K1 : K0;
+                T s2 = 0;
+                if (col < kr) for (int k = 0; k < Kp; ++k) { const T v = Tm[p * bst + col * ldt + k]; s2 += v * v; }
+                nrm[e] = (col < kr && Kp > 0) ? sqrt(s2) : (T)-1;
+            }
+            __syncthreads();
+            int kk = chi < K0 + K1 ? chi : K0 + K1;
+            if (2 * kr < kk) kk = 2 * kr;
+            for (int e = tid; e < 2 * n; e += NT) {
+                const T v = nrm[e];
+                int rk = 0;
+                for (int o = 0; o < 2 * n; ++o) { const T w = nrm[o]; rk += (w > v) || (w == v && o < e); }
+                rankv[e] = (v >= (T)0) ? rk : 1 << 20;
+            }
+            __syncthreads();
+            // new left bond: kept columns of block 0 (by rank), then of block 1
+            if (tid == 0) {
+                int s0 = 0, s1 = 0;
+                for (int e = 0; e < 2 * n; ++e) if (rankv[e] < kk) { if (e < n) ++s0; else ++s1; }
+                iflag[1] = s0; iflag[2] = s1;
+            }
+            __syncthreads();
+            const int s0 = iflag[1];
+            for (int e = tid; e < 2 * n; e += NT) {
+                if (rankv[e] < kk) {
+                    const int p = e / n;
+                    int pos = 0;
+                    for (int o = p * n; o < p * n + n; ++o) pos += rankv[o] < rankv[e];
+                    colof[(p ? s0 : 0) + pos] = e;
+                }
+            }
+            double kp = 0.0;
+            for (int e = tid; e < 2 * n; e += NT) if (rankv[e] < kk) { const double v = (double)nrm[e]; kp += v * v; }
+            const double nk = sqrt(block_sum(kp, red));   // (block_sum syncs)
+            ls += log(nk);
+            // new site c (right-canonical): slot a <- column colof[a]
+            for (int e = tid; e < cc2; e += NT) {
+                const int a = e / chi, m = e % chi;
+                T v0 = 0, v1 = 0;
+                if (a < kk && m < kr) {
+                    const int ce = colof[a], p = ce / n, col = ce % n;
+                    const int pm = m >= r0, mm = pm ? m - r0 : m;
+                    const int dp = p ? r1 : r0;
+                    // physical parity s = p ^ pm; row of W^p for (s, m)
+                    const int s = p ^ pm;
+                    const int row = (s == 0) ? mm : dp + mm;
+                    const T w = Wm[p * bst + col * ldt + row];
+                    if (s == 0) v0 = w; else v1 = w;
+                }
+                put_site(r, c, a, m, v0, v1);
+            }
+            if (r == 0) {
+                // row-0 contraction from the right on the even physical component
+                double *u = uvec, *un = uvec + 64;
+                for (int a = tid; a < kk; a += NT) {
+                    const int ce = colof[a], p = ce / n, col = ce % n;
+                    double acc = 0.0;
+                    // s = 0 entries: m in sector p, row = index within the sector
+                    const int dp = p ? r1 : r0, off = p ? r0 : 0;
+                    for (int mm = 0; mm < dp; ++mm) acc += (double)Wm[p * bst + col * ldt + mm] * u[off + mm];
+                    un[a] = acc;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    double mx = 0.0;
+                    for (int a = 0; a < kk; ++a) mx = fmax(mx, fabs(un[a]));
+                    scal[2] = mx > 0.0 ? mx : 1.0;
+                }
+                __syncthreads();
+                const double mx = scal[2];
+                for (int a = tid; a < kk; a += NT) u[a] = un[a] / mx;
+                ulog += log(mx);
+            }
+            __syncthreads();
+            // X^p (K_p x d'^p) = U S / ||S_kept|| for the next site
+            const T inv = (T)(1.0 / nk);
+            for (int e = tid; e < 2 * chi * chi; e += NT) {
+                const int p = e / cc2, k = (e / chi) % chi, j = e % chi;
+                const int Kp = p ? K1 : K0, dp = p ? kk - s0 : s0;
+                if (k < Kp && j < dp) {
+                    const int ce = colof[(p ? s0 : 0) + j];
+                    X[e] = Tm[p * bst + (ce % n) * ldt + k] * inv;
+                }
+            }
+            if (tid == 0) { dsec[2 * c] = (unsigned char)s0; dsec[2 * c + 1] = (unsigned char)(kk - s0); }
+            __syncthreads();
+        }
+        cyc_svd += wall_clock64() - ts0;
+        if (tid == 0) lsc[r] = ls;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double lz = logz_tail;
+        for (int r = 0; r < L; ++r) lz += lsc[r];
+        if (logz_out) logz_out[inst] = lz;
+        if (stats_out) {
+            int64_t *so = stats_out + STATS_PER_INST * inst;
+            so[0] = total_sweeps;
+            so[1] = cyc_qr;
+            so[2] = cyc_svd;
+            so[3] = cyc_jac;
+            so[4] = t_begin;
+            so[5] = wall_clock64();
+            so[7] = cyc_hh;
+        }
+    }
+}
+
+// Shared-memory bytes the build needs for bond dimension chi and side L.
+size_t build_lds_bytes(int chi, int L, size_t tsize);
+
+}  // namespace tnmc

@@ -1,0 +1,196 @@
+// Row-by-row autoregressive sampling from the boundary-MPS cache
+// (arXiv 2509.19006, section 3.3; chain rule Eq. (3) in raster order,
+// conditional Eq. (4), sigmoid form Eq. (5)).
+//
+// A workgroup of NTS threads owns a tile of NTS samples of one instance, one
+// sample per thread.  For every row r:
+//   right sweep  R_{L-1} = e_0;  R_c = sum_s Bv(r-1,c+1)[u_{c+1}, s] A_{c+1,s} R_{c+1}
+//                (u = the sample's spins of row r-1), rescaled by a power of
+//                two and kept in a per-tile scratch [c][a][sample];
+//   left sweep   l = e_0;  rho_s = |l A_{c,s} R_c|;
+//                logit = ln rho_+ - ln rho_- + 2 beta J_v(r-1,c) u_c (+ MLP);
+//                p = sigmoid(logit) in float64; spin = +1 iff Philox u < p
+//                (or the given spin when scoring); log q += ln p or ln(1-p);
+//                l = l A_{c,spin}, rescaled by a power of two.
+// Each cache site (both spin slices, CHI x CHI, zero padded) is staged in
+// shared memory once and read by every sample of the instance.
+#pragma once
+#include <type_traits>
+
+#include "mlp_device.hpp"
+
+namespace tnmc {
+
+constexpr int NTS = 256;
+
+// Learned correction (optional): parameter vector in the layout of
+// mlp_device.hpp and the horizontal couplings for the features.
+struct MlpArgs {
+    const float *params;
+    const float *Jh;
+};
+
+// One tile of NTS samples of instance inst (all threads of the workgroup
+// call it).  env: the tile's right-environment scratch; As, Ps: shared
+// arrays for the staged site and the network weights.
+template <typename T, typename S, int CHI, bool HAS_MLP>
+__device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char *__restrict__ ws, T *env,
+                            int n_samples, uint64_t seed, uint64_t sample_offset,
+                            const uint64_t *__restrict__ forced, uint64_t *spins_out,
+                            double *__restrict__ logq_out, float *__restrict__ logits_out,
+                            const float *__restrict__ Jv_all, MlpArgs mlp, T (*As)[CHI][CHI], float *Ps) {
+    const int tid = threadIdx.x;
+    const int n = tile * NTS + tid;
+    const bool act = n < n_samples;
+    const int L = d.L, chi = d.chi, W = d.W;
+    const double beta = d.beta;
+    const S *cache = reinterpret_cast<const S *>(ws + d.cache_off);
+    const size_t site_sz = (size_t)2 * chi * chi, row_sz = (size_t)L * site_sz;
+    const float *jv = Jv_all + d.off_v;
+    const size_t wbase = (size_t)n_samples * d.word_prefix + (size_t)n * L * W;
+    uint64_t *my_out = spins_out + wbase;
+    const uint64_t *my_forced = forced ? forced + wbase : nullptr;
+    float *my_logits = logits_out ? logits_out + (size_t)n_samples * d.site_prefix + (size_t)n * L * L : nullptr;
+    const uint32_t sidx = (uint32_t)(sample_offset + (uint64_t)n);
+
+    const float *jh = HAS_MLP ? mlp.Jh + d.off_h : nullptr;
+    if (HAS_MLP) {
+        // weights rounded to bfloat16 (float32 accumulation)
+        for (int e = tid; e < MLP_NPARAM; e += NTS) Ps[e] = __bfloat162float(__float2bfloat16(mlp.params[e]));
+    }
+    auto stage = [&](const S *site) {
+        for (int e = tid; e < 2 * CHI * CHI; e += NTS) {
+            const int s = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
+            As[s][a][b] = (a < chi && b < chi) ? load_as<T, S>(site + (size_t)s * chi * chi + a * chi + b) : (T)0;
+        }
+    };
+
+    double logq = 0.0;
+    for (int r = 0; r < L; ++r) {
+        const S *crow = cache + (size_t)r * row_sz;
+        // ---------------- right environments ----------------
+        {
+            T R[CHI];
+#pragma unroll
+            for (int a = 0; a < CHI; ++a) R[a] = (a == 0) ? (T)1 : (T)0;
+            int uw_idx = -1;
+            uint64_t uw = 0;
+            for (int c = L - 2; c >= 0; --c) {
+                __syncthreads();
+                stage(crow + (size_t)(c + 1) * site_sz);
+                __syncthreads();
+                if (!act) continue;
+                T w0 = 1, w1 = 1;
+                if (r > 0) {
+                    const int cc = c + 1, wi = cc >> 6;
+                    if (wi != uw_idx) { uw = my_out[(size_t)(r - 1) * W + wi]; uw_idx = wi; }
+                    const int u = (int)((uw >> (cc & 63)) & 1);
+                    double same, diff;
+                    boltz(beta, jv[(size_t)(r - 1) * L + cc], same, diff);
+                    w0 = (T)(u == 0 ? same : diff);
+                    w1 = (T)(u == 1 ? same : diff);
+                }
+                T Rn[CHI];
+                T mx = 0;
+#pragma unroll
+                for (int a = 0; a < CHI; ++a) {
+                    T z0 = 0, z1 = 0;
+#pragma unroll
+                    for (int b = 0; b < CHI; ++b) { z0 += As[0][a][b] * R[b]; z1 += As[1][a][b] * R[b]; }
+                    Rn[a] = w0 * z0 + w1 * z1;
+                    mx = fmax(mx, fabs(Rn[a]));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const T sc = mx > (T)0 ? pow2_inv(mx) : (T)1;
+                T *ec = env + (size_t)c * CHI * NTS + tid;
+#pragma unroll
+                for (int a = 0; a < CHI; ++a) { R[a] = Rn[a] * sc; ec[(size_t)a * NTS] = R[a]; }
+            }
+        }
+        // ---------------- left sweep: sample the row ----------------
+        {
+            T l[CHI];
+#pragma unroll
+            for (int a = 0; a < CHI; ++a) l[a] = (a == 0) ? (T)1 : (T)0;
+            uint64_t cur = 0, up = 0, fw = 0;
+            for (int c = 0; c < L; ++c) {
+                __syncthreads();
+                stage(crow + (size_t)c * site_sz);
+                __syncthreads();
+                if (!act) continue;
+                // y_s = l A_{c,s} for both spins; every staged value is read once
+                T y0[CHI], y1[CHI];
+#pragma unroll
+                for (int b = 0; b < CHI; ++b) { y0[b] = 0; y1[b] = 0; }
+#pragma unroll
+                for (int a = 0; a < CHI; ++a) {
+                    const T la = l[a];
+#pragma unroll
+                    for (int b = 0; b < CHI; ++b) { y0[b] += la * As[0][a][b]; y1[b] += la * As[1][a][b]; }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // rho_s = y_s . R_c  (R_{L-1} = e_0)
+                T r0, r1;
+                if (c == L - 1) {
+                    r0 = y0[0]; r1 = y1[0];
+                } else {
+                    const T *ec = env + (size_t)c * CHI * NTS + tid;
+                    r0 = 0; r1 = 0;
+#pragma unroll
+                    for (int b = 0; b < CHI; ++b) { const T rb = ec[(size_t)b * NTS]; r0 += y0[b] * rb; r1 += y1[b] * rb; }
+                }
+                const double rho0 = fabs((double)r0), rho1 = fabs((double)r1);
+                double logit = 0.0;
+                if ((c & 63) == 0) {
+                    if (r > 0) up = my_out[(size_t)(r - 1) * W + (c >> 6)];
+                    if (my_forced) fw = my_forced[(size_t)r * W + (c >> 6)];
+                }
+                if (rho0 > 0.0 || rho1 > 0.0) {
+                    logit = log(rho1) - log(rho0);
+                    if (r > 0) {
+                        const double u = (double)((up >> (c & 63)) & 1);
+                        logit += 2.0 * beta * (double)jv[(size_t)(r - 1) * L + c] * (2.0 * u - 1.0);
+                    }
+                }
+                if (HAS_MLP) {
+                    // spins already fixed: rows above from the output, row r
+                    // from the word being assembled (or the flushed one)
+                    const uint64_t curw = cur;
+                    auto spin = [&](int rr, int cc) -> float {
+                        uint64_t w;
+                        if (rr == r && (cc >> 6) == (c >> 6)) w = curw;
+                        else w = my_out[(size_t)rr * W + (cc >> 6)];
+                        return ((w >> (cc & 63)) & 1) ? 1.f : -1.f;
+                    };
+                    float x[MLP_IN];
+                    mlp_features(jh, jv, L, r, c, spin, (float)logit, x);
+                    logit += (double)mlp_forward(Ps, x);
+                }
+                int spin;
+                if (my_forced) {
+                    spin = (int)((fw >> (c & 63)) & 1);
+                } else {
+                    const double p = 1.0 / (1.0 + exp(-logit));
+                    const double u = philox_unit(seed, (uint32_t)(r * L + c), sidx, (uint32_t)inst, 0u);
+                    spin = (u < p) ? 1 : 0;
+                }
+                logq += spin ? log_sigmoid(logit) : log_sigmoid(-logit);
+                if (my_logits) my_logits[(size_t)r * L + c] = (float)logit;
+                cur |= (uint64_t)spin << (c & 63);
+                if ((c & 63) == 63 || c == L - 1) { my_out[(size_t)r * W + (c >> 6)] = cur; cur = 0; }
+                T ln[CHI];
+                T mx = 0;
+#pragma unroll
+                for (int b = 0; b < CHI; ++b) ln[b] = spin ? y1[b] : y0[b];
+#pragma unroll
+                for (int b = 0; b < CHI; ++b) mx = fmax(mx, fabs(ln[b]));
+                const T sc = mx > (T)0 ? pow2_inv(mx) : (T)1;
+#pragma unroll
+                for (int b = 0; b < CHI; ++b) l[b] = ln[b] * sc;
+            }
+        }
+    }
+    if (act) logq_out[(size_t)inst * n_samples + n] = logq;
+}
+
+}  // namespace tnmc

@@ -94,3 +94,50 @@ def test_decode_steps_replay_from_a_graph(tnmc):
             assert torch.equal(a, b), rep
         E.add_(1.0)                   # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_fused_pipeline_equals_separate_calls(tnmc, prec):
+    """tnmc_run (build, sampling tiles, energies and the chain in one
+    persistent launch) gives bit-identical results to tnmc_build_env +
+    tnmc_sample + tnmc_energy + tnmc_accept on an uneven batch; 300 samples
+    span two sample tiles, run one after the other in the fused launch."""
+    import torch
+    import tnmc_gpu as G
+    Ls = [6, 12, 20, 9, 16, 24]
+    chis = [4, 16, 8, 2, 32 if prec != 0 else 16, 8]
+    fams = ["pmj", "gauss", "pmj", "gauss", "gauss", "pmj"]
+    betas = workloads.betas_uniform(len(Ls), 0.5, 2.0, 92)
+    Js = [workloads.instance(L, f, 92, i) for i, (L, f) in enumerate(zip(Ls, fams))]
+    G.say(f"fused pipeline vs separate calls, prec {prec}")
+    jh = torch.as_tensor(np.concatenate([a.ravel() for a, _ in Js])).cuda()
+    jv = torch.as_tensor(np.concatenate([b.ravel() for _, b in Js])).cuda()
+    p = tnmc.Problem(jh, jv, Ls, chis, betas)
+    B, n = len(Ls), 300
+    out = []
+    for fused in (False, True):
+        ws = torch.zeros(tnmc.tnmc_workspace_size(p, prec, n), dtype=torch.uint8, device="cuda")
+        spins = torch.zeros(n * p.spin_words_per_sample(), dtype=torch.int64, device="cuda")
+        logq = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+        E = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+        acc = torch.zeros((B, n), dtype=torch.uint8, device="cuda")
+        st = torch.zeros((B, n), dtype=torch.int64, device="cuda")
+        logz = torch.zeros(B, dtype=torch.float64, device="cuda")
+        chain = torch.zeros(B * tnmc.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
+        if fused:
+            env = tnmc.tnmc_run(p, prec, ws, n, 21, chain, 22, spins, logq, E, acc, st, logz,
+                                sample_offset=7, step_offset=7)
+        else:
+            env = tnmc.tnmc_build_env(p, prec, ws, logz)
+            tnmc.tnmc_sample(env, n, 21, spins, logq, sample_offset=7)
+            tnmc.tnmc_energy(env, n, spins, E)
+            bt = torch.as_tensor(np.asarray(betas, np.float64)).cuda()
+            tnmc.tnmc_accept(logq, E, bt, chain, 22, 7, acc, st)
+        torch.cuda.synchronize()
+        stats = tnmc.tnmc_env_stats(env)
+        out.append([t.cpu().numpy() for t in (spins, logq, E, acc, st, logz, chain)] + [stats])
+    for a, b in zip(out[0][:7], out[1][:7]):
+        assert np.array_equal(a, b)
+    # the fused launch records each instance's completion after its build
+    st = out[1][7]
+    assert np.all(st[:, 6] > st[:, 5]) and np.all(st[:, 5] > st[:, 4])
