@@ -158,6 +158,62 @@ def cpu_baseline(L, chi, beta, N, acceptance, jh, jv, build_rows=36, sample_rows
                        f"{N} samples; acceptance taken from the float32 GPU run")}
 
 
+def c4_spec():
+    """The uneven batch: 512 instances, L in {32, 64, 128, 256} (equal
+    counts), +-J when floor(i/4) is even else Gaussian, chi in {16, 32, 64}
+    by floor(i/8) mod 3, beta uniform in [0.5, 2.0]."""
+    import workloads
+    betas = workloads.betas_uniform(512, 0.5, 2.0, 4)
+    return [((32, 64, 128, 256)[i % 4], "pmj" if (i // 4) % 2 == 0 else "gauss",
+             (16, 32, 64)[(i // 8) % 3], float(betas[i])) for i in range(512)]
+
+
+def run_uneven(args):
+    """Uneven batch in one persistent launch per schedule; the schedule comes
+    from the autotuner (candidates timed on a 1/4-scale replica)."""
+    import numpy as np
+    import paper_2509_19006_amd as T
+    from paper_2509_19006_amd import autotune
+    import workloads
+    T.load()
+    spec = c4_spec()
+    N = 32
+    log(f"uneven batch: {len(spec)} instances, {N} samples each; tuning the schedule on a 1/4-scale replica "
+        f"(objective {args.objective})")
+    name, mode, order, table = autotune.tune(lambda L, fam, i: workloads.instance(L, fam, 40, i), spec, T.FP32,
+                                             N, objective=args.objective, scale=4)
+    for k, (v, r) in table.items():
+        c = r["completion_s"]
+        log(f"  {k}: {args.objective} {v:.3f} s, wall {r['wall_s']:.3f} s, p50 {np.percentile(c, 50):.3f} s, "
+            f"p99 {np.percentile(c, 99):.3f} s")
+    log(f"chosen: {name}; full batch ...")
+    Js = [workloads.instance(L, fam, 4, i) for i, (L, fam, _, _) in enumerate(spec)]
+    res = autotune.run_schedule(Js, [c for _, _, c, _ in spec], [b for _, _, _, b in spec], T.FP32, N, mode, order)
+    c = res["completion_s"]
+    by_class = {}
+    for (L, _, chi, _), t in zip(spec, c):
+        by_class.setdefault(f"L{L}_chi{chi}", []).append(t)
+    line = {
+        "metric": "accepted samples/s, uneven batch in one persistent launch, + p50/p99 per-instance completion",
+        "value": res["accepted"] / res["wall_s"], "unit": "accepted samples/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": res["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven batch: 512 instances, L in {32,64,128,256}, half +-J half Gaussian, "
+                               "beta in [0.5, 2], chi in {16,32,64}, 32 samples each, float32",
+                   "schedule": name, "objective": args.objective},
+        "proposals_per_s": len(spec) * N / res["wall_s"],
+        "acceptance": res["accepted"] / max(1, res["trials"]),
+        "completion_p50_s": float(np.percentile(c, 50)), "completion_p99_s": float(np.percentile(c, 99)),
+        "completion_max_s": float(c.max()),
+        "completion_median_by_class_s": {k: float(np.median(v)) for k, v in sorted(by_class.items())},
+        "tuner_replica": {k: {"objective": v, "wall_s": r["wall_s"],
+                              "p50_s": float(np.percentile(r["completion_s"], 50)),
+                              "p99_s": float(np.percentile(r["completion_s"], 99))}
+                          for k, (v, r) in table.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +227,11 @@ def main():
     ap.add_argument("--mixed", choices=["bf16", "fp16"], default="fp16")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["mixed", "uneven"], default="mixed",
+                    help="mixed: the headline 256x256 batch (default); uneven: the 512-instance mix in one "
+                         "persistent launch with an autotuned schedule")
+    ap.add_argument("--objective", choices=["p99", "p50", "mean", "makespan"], default="p99",
+                    help="what the schedule autotuner minimises (uneven workload)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of this many GiB three times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -190,6 +251,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"copy probe: 3 copies of {n} bytes")
+        return
+    if args.workload == "uneven":
+        run_uneven(args)
         return
     import paper_2509_19006_amd as T
     import workloads

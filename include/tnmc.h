@@ -66,6 +66,11 @@ extern "C" {
 #define TNMC_MIXED_FP16  3 /* as MIXED_BF16 with float16 cache storage       */
 
 /* largest bond dimension and lattice side the kernels are built for */
+/* launch orders of tnmc_run */
+#define TNMC_SCHED_LONGEST_FIRST  0  /* decreasing (L-1) L chi^3: shortest batch */
+#define TNMC_SCHED_SHORTEST_FIRST 1  /* increasing cost: small instances done early */
+#define TNMC_SCHED_AS_GIVEN       2  /* the problem's instance order            */
+
 #define TNMC_CHI_MAX  64
 #define TNMC_L_MAX    1024
 
@@ -152,13 +157,16 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision,
  *  spins_out, logq_out, E_out, accepted_out, state_out   as the outputs of
  *             tnmc_sample, tnmc_energy and tnmc_accept (state_out may be
  *             NULL).
+ *  schedule   TNMC_SCHED_*: the order in which workgroups take instances
+ *             (tnmc_build_env always runs longest-first).
  * Errors as tnmc_build_env; on error no env is returned.                    */
 int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace,
              size_t workspace_bytes, int32_t n_samples, uint64_t sample_seed,
              uint64_t sample_offset, tnmc_chain *chain, uint64_t accept_seed,
              uint64_t step_offset, uint64_t *spins_out, double *logq_out,
              double *E_out, uint8_t *accepted_out, int64_t *state_out,
-             double *logz_out, void *stream, tnmc_env **env_out);
+             double *logz_out, int32_t schedule, void *stream,
+             tnmc_env **env_out);
 
 /* Draw (or score) n_samples configurations per instance (section 3.3).
  *  seed, sample_offset  Philox key and first global sample index.

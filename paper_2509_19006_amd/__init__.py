@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so"
 
 TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP = 0, -1, -2, -3, -4
 FP64, FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
+SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
 CHAIN_BYTES = 48           # sizeof(tnmc_chain)
 
@@ -61,7 +62,7 @@ def load(path: str = LIB_PATH):
     lib.tnmc_build_env.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p), c_void_p]
     lib.tnmc_run.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_int32, c_uint64, c_uint64, c_void_p,
                              c_uint64, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                             c_void_p, P(c_void_p)]
+                             c_int32, c_void_p, P(c_void_p)]
     lib.tnmc_sample.argtypes = [c_void_p, c_int32, c_uint64, c_uint64, c_void_p, P(_Mlp), c_void_p,
                                 c_void_p, c_void_p, c_void_p]
     lib.tnmc_energy.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
@@ -168,15 +169,17 @@ def tnmc_build_env(problem: Problem, precision: int, workspace, logz_out=None, s
 
 def tnmc_run(problem: Problem, precision: int, workspace, n_samples: int, sample_seed: int, chain,
              accept_seed: int, spins_out, logq_out, E_out, accepted_out, state_out=None, logz_out=None,
-             sample_offset: int = 0, step_offset: int = 0, stream=None) -> Env:
+             sample_offset: int = 0, step_offset: int = 0, schedule: int = 0, stream=None) -> Env:
     """Build, sample, score and accept every instance in one persistent
-    launch (each instance finishes on its own); returns the env."""
+    launch (each instance finishes on its own); schedule is one of
+    SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN.  Returns the
+    env."""
     lib = load()
     h = c_void_p(0)
     _check(lib.tnmc_run(byref(problem._c), precision, _ptr(workspace), workspace.numel(), n_samples,
                         sample_seed, sample_offset, _ptr(chain), accept_seed, step_offset, _ptr(spins_out),
                         _ptr(logq_out), _ptr(E_out), _ptr(accepted_out), _ptr(state_out), _ptr(logz_out),
-                        _stream(stream), byref(h)))
+                        schedule, _stream(stream), byref(h)))
     return Env(h, problem, precision, workspace)
 
 

@@ -117,7 +117,7 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
 
 // Workspace layout: [desc table][build stats][per instance: log-scales,
 // cache, build scratch, previous-row ping-pong][sampler env tiles ...].
-int plan(const tnmc_problem *p, int precision, Plan &pl) {
+int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCHED_LONGEST_FIRST) {
     const size_t ts = tsize_of(precision), ss = ssize_of(precision);
     const int B = p->batch;
     pl.desc.assign(B, InstDesc{});
@@ -133,16 +133,17 @@ int plan(const tnmc_problem *p, int precision, Plan &pl) {
     off = align_up(off + sizeof(int32_t) * B);
     pl.sweeps_off = off;
     off = align_up(off + sizeof(int64_t) * tnmc::STATS_PER_INST * B);
-    // Longest-processing-time-first: the build of an instance costs about
-    // (L-1) L chi^3, and instances that start first finish first on a full
-    // machine, so the launch order is by decreasing cost (stable on ties).
+    // Launch order.  The build of an instance costs about (L-1) L chi^3 and
+    // workgroups start in launch order, so longest-first (the default)
+    // shortens the whole batch; shortest-first lets small instances finish
+    // early; or the problem's own order.  Stable on ties.
     pl.order.resize(B);
     for (int i = 0; i < B; ++i) pl.order[i] = i;
-    std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) {
-        const double ca = (double)(p->L[a] - 1) * p->L[a] * std::pow((double)p->chi[a], 3);
-        const double cb = (double)(p->L[b] - 1) * p->L[b] * std::pow((double)p->chi[b], 3);
-        return ca > cb;
-    });
+    auto cost = [&](int i) { return (double)(p->L[i] - 1) * p->L[i] * std::pow((double)p->chi[i], 3); };
+    if (schedule == TNMC_SCHED_LONGEST_FIRST)
+        std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    else if (schedule == TNMC_SCHED_SHORTEST_FIRST)
+        std::stable_sort(pl.order.begin(), pl.order.end(), [&](int a, int b) { return cost(a) < cost(b); });
     int64_t oh = 0, ov = 0, wp = 0, sp = 0;
     for (int i = 0; i < B; ++i) {
         InstDesc &d = pl.desc[i];
@@ -213,13 +214,14 @@ namespace {
 // Validates, plans the workspace, creates the env and uploads descriptors
 // and launch order; the caller launches the kernels.
 int setup_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
-              hipStream_t st, tnmc_env **env_out, Plan &pl) {
+              hipStream_t st, tnmc_env **env_out, Plan &pl, int schedule = TNMC_SCHED_LONGEST_FIRST) {
     int rc = validate(p, precision, true);
     if (rc) return rc;
     if (!env_out) return fail(TNMC_EINVAL, "env_out is NULL");
     if (!workspace) return fail(TNMC_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(TNMC_EINVAL, "workspace must be 256-byte aligned");
-    plan(p, precision, pl);
+    if (schedule < TNMC_SCHED_LONGEST_FIRST || schedule > TNMC_SCHED_AS_GIVEN) return fail(TNMC_EINVAL, "unknown schedule");
+    plan(p, precision, pl, schedule);
     if (workspace_bytes < pl.fixed + pl.tile_bytes)
         return fail(TNMC_ENOSPACE, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs at least " + std::to_string(pl.fixed + pl.tile_bytes));
     rc = check_lds(precision, pl.chi_max, pl.L_max);
@@ -281,15 +283,15 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
 int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace, size_t workspace_bytes,
              int32_t n_samples, uint64_t sample_seed, uint64_t sample_offset, tnmc_chain *chain,
              uint64_t accept_seed, uint64_t step_offset, uint64_t *spins_out, double *logq_out,
-             double *E_out, uint8_t *accepted_out, int64_t *state_out, double *logz_out, void *stream,
-             tnmc_env **env_out) {
+             double *E_out, uint8_t *accepted_out, int64_t *state_out, double *logz_out, int32_t schedule,
+             void *stream, tnmc_env **env_out) {
     if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
     if (!spins_out || !logq_out || !E_out || !accepted_out || !chain)
         return fail(TNMC_EINVAL, "spins_out, logq_out, E_out, accepted_out and chain must be non-NULL");
     Plan pl;
     hipStream_t st = static_cast<hipStream_t>(stream);
     tnmc_env *env = nullptr;
-    int rc = setup_env(p, precision, workspace, workspace_bytes, st, &env, pl);
+    int rc = setup_env(p, precision, workspace, workspace_bytes, st, &env, pl, schedule);
     if (rc) return rc;
     const int32_t *ord = reinterpret_cast<const int32_t *>(env->ws + pl.order_off);
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
