@@ -151,7 +151,8 @@ __device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, 
 }
 
 // One-sided (Hestenes) Jacobi on one block, run by a single wave with the
-// block in registers.  The block has n columns (n even, n <= CHI) of length
+// block and its accumulated rotation W in registers (the form for chi <= 32,
+// where a step is bound by its dependency chain, not by issue).  The block has n columns (n even, n <= CHI) of length
 // K <= CHI at Tb, column-major with leading dimension ld; columns n..CHI-1
 // are treated as zero and never rotate.  Column pairs follow the odd-even
 // transposition order over CHI positions: even steps pair positions
@@ -171,7 +172,7 @@ __device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, 
 // the rotated block is back at Tb and W (n x n, same leading dimension) at
 // Wb.  Returns the sweep count.
 template <typename T, int CHI>
-__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane) {
+__device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
     constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
     int g = lane / G, gl = lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
@@ -266,17 +267,165 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane) {
     return sweeps;
 }
 
+// One-sided (Hestenes) Jacobi on one block with the block in one wave's
+// registers and the accumulated rotation W in a second wave's (the form for
+// chi = 64, where a step's instruction count, not its dependency chain,
+// sets its length).  The block
+// has n columns (n even, n <= CHI) of length K <= CHI at Tb, column-major
+// with leading dimension ld; columns n..CHI-1 are treated as zero and never
+// rotate.  Column pairs follow the odd-even transposition order over CHI
+// positions: even steps pair positions (2g, 2g+1), odd steps (2g+1, 2g+2)
+// with positions 0 and CHI-1 idle, and every pair swaps positions after its
+// step; CHI steps meet every pair once and reverse the order.  Each wave
+// splits into CHI/2 lane groups of G = 128/CHI lanes; group g holds the two
+// columns of its pair (rows strided over its lanes).  Going from an even to
+// an odd step a group takes the second column of the next group; going
+// back, the first column of the previous group (the last group, idle in odd
+// steps, hands over its second): one move per column and step, through the
+// LDS permute crossbar.
+//   role 0 (the block): squared column norms are recomputed every sweep and
+//   carried through each rotation exactly (a' = a - t*g, b' = b + t*g), so a
+//   pair needs one reduction; pairs whose smaller column is below
+//   sqrt(n)*eps*||T||_F are left alone (rounding noise, on which a relative
+//   orthogonality test never settles).  Each step's (cos, sin) per group go
+//   to prm before the workgroup barrier that ends the step.
+//   role 1 (W, starting from the identity): after that barrier it applies
+//   the same step's rotations, one step behind the block.
+// All four waves of the workgroup call this together (the two blocks' role 0
+// and role 1 waves): the barriers are workgroup-wide, so both blocks sweep
+// until neither rotates (extra sweeps of a converged block rotate nothing).
+// prm: [2 blocks][2 slots][CHI/2][2], flags: [2].  On return the rotated
+// block is back at Tb (role 0) and W (n x n, same leading dimension) at Wb
+// (role 1).  Returns the sweep count.
+template <typename T, int CHI>
+__device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, int p, T *prm, int *flags) {
+    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
+    int g = lane / G, gl = lane % G;
+    asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
+    const bool blk = (role == 0);
+    T x[RK], y[RK];
+#pragma unroll
+    for (int i = 0; i < RK; ++i) {
+        const int row = gl + G * i;
+        if (blk) {
+            x[i] = (row < K && 2 * g < n) ? Tb[(2 * g) * ld + row] : (T)0;
+            y[i] = (row < K && 2 * g + 1 < n) ? Tb[(2 * g + 1) * ld + row] : (T)0;
+        } else {
+            x[i] = (row == 2 * g) ? (T)1 : (T)0;
+            y[i] = (row == 2 * g + 1) ? (T)1 : (T)0;
+        }
+    }
+    const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
+    const bool last = (g == HP - 1);
+    const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
+    const T tol2 = tol * tol;
+    T *pp = prm + p * 4 * HP;
+    T small = 0;
+    int sweeps = 0, slot = 0;
+    for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
+        T a = 0, b = 0;
+        if (blk) {
+#pragma unroll
+            for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
+            if (sw == 0) small = group_sum(a + b, 64) * (T)(1.0 / G) * Eps<T>::v * Eps<T>::v * (T)n;
+            a = group_sum(a, G);
+            b = group_sum(b, G);
+        }
+        bool rot = false;
+        for (int t = 0; t < CHI; t += 2) {
+#pragma unroll
+            for (int odd = 0; odd < 2; ++odd) {
+                T cs = 1, sn = 0;
+                T *ps = pp + (slot * HP + g) * 2;
+                if (blk) {
+                    T c0 = 0, c1 = 0;
+#pragma unroll
+                    for (int i = 0; i < RK; i += 2) {
+                        c0 += x[i] * y[i];
+                        if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
+                    }
+                    const T c = group_sum(c0 + c1, G);
+                    T tt;
+                    rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn, tt);
+                    if (gl == 0) { ps[0] = cs; ps[1] = sn; }
+                    a -= tt * c;
+                    b += tt * c;
+                }
+                __syncthreads();
+                if (!blk) {
+                    cs = ps[0];
+                    sn = ps[1];
+                }
+                slot ^= 1;
+#pragma unroll
+                for (int i = 0; i < RK; ++i) {
+                    const T u = x[i], v = y[i];
+                    x[i] = cs * u - sn * v;
+                    y[i] = sn * u + cs * v;
+                }
+                if (!odd) {
+                    // even -> odd layout: second column from the next group
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) y[i] = bperm<T>(up, y[i]);
+                    if (blk) b = bperm<T>(up, b);
+                } else {
+                    // odd -> even layout: first column from the previous
+                    // group; the idle last group keeps its first as second
+                    // and hands over its second
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) {
+                        const T nx = bperm<T>(dn, last ? y[i] : x[i]);
+                        y[i] = last ? x[i] : y[i];
+                        x[i] = nx;
+                    }
+                    if (blk) {
+                        const T na = bperm<T>(dn, last ? b : a);
+                        b = last ? a : b;
+                        a = na;
+                    }
+                }
+            }
+        }
+        ++sweeps;
+        const bool any = __ballot(rot) != 0;
+        if (blk && lane == 0) flags[p] = any;
+        __syncthreads();
+        const bool more = flags[0] || flags[1];
+        if (!more) break;
+    }
+    // after an odd number of sweeps the positions are reversed
+    const bool rev = sweeps & 1;
+    const int cx = rev ? CHI - 1 - 2 * g : 2 * g, cy = rev ? CHI - 2 - 2 * g : 2 * g + 1;
+#pragma unroll
+    for (int i = 0; i < RK; ++i) {
+        const int row = gl + G * i;
+        if (blk) {
+            if (row < K) {
+                if (cx < n) Tb[cx * ld + row] = x[i];
+                if (cy < n) Tb[cy * ld + row] = y[i];
+            }
+        } else if (row < n) {
+            if (cx < n) Wb[cx * ld + row] = x[i];
+            if (cy < n) Wb[cy * ld + row] = y[i];
+        }
+    }
+    return sweeps;
+}
+
 // The register Jacobi for the smallest compiled width that holds chi; MAXB
 // is the widest one compiled into this kernel (wider paths only cost
-// registers, so a kernel carries the ones its launch needs).
+// registers, so a kernel carries the ones its launch needs).  Called by all
+// four waves: for chi <= 32 waves 0 and 1 each run one block alone; for
+// chi = 64 waves 2 and 3 carry the blocks' rotations (role 1).
 template <typename T, int MAXB>
-__device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane) {
-    if (chi <= 16) return jacobi_reg<T, 16>(Tb, Wb, ld, K, n, lane);
-    if constexpr (MAXB <= 32) return jacobi_reg<T, 32>(Tb, Wb, ld, K, n, lane);
-    else {
-        if (chi <= 32) return jacobi_reg<T, 32>(Tb, Wb, ld, K, n, lane);
-        return jacobi_reg<T, 64>(Tb, Wb, ld, K, n, lane);
+__device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
+                            int *flags) {
+    if constexpr (MAXB >= 64) {
+        if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
     }
+    if (role != 0) return 0;
+    if (chi <= 16) return jacobi_one<T, 16>(Tb, Wb, ld, K, n, lane);
+    return jacobi_one<T, 32>(Tb, Wb, ld, K, n, lane);
 }
 
 // One site of the QR sweep for both parity blocks, held in registers.
@@ -506,14 +655,16 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
     T *tau = tail;                    // [2][CB]
     T *nrm = tau + 2 * CB;            // [2][chi+2]
+    T *jprm = nrm + 2 * (chi + 2);    // [2][2][CB/2][2] Jacobi rotations in flight
     double *red = reinterpret_cast<double *>(
-        (reinterpret_cast<uintptr_t>(nrm + 2 * (chi + 2)) + 7) & ~(uintptr_t)7);
+        (reinterpret_cast<uintptr_t>(jprm + 4 * CB) + 7) & ~(uintptr_t)7);
     double *uvec = red + NT / 64;     // [2][64] row-0 contraction vector
     double *scal = uvec + 128;        // [8]
     int *colof = reinterpret_cast<int *>(scal + 8);   // [2chi+4] kept column of new bond slot
     int *rankv = colof + 2 * chi + 4;                 // [2chi+4]
     int *iflag = rankv + 2 * chi + 4;                 // [4]
-    unsigned char *dsec = reinterpret_cast<unsigned char *>(iflag + 4);  // [L+1][2] bond sectors
+    int *jflag = iflag + 4;                           // [2] Jacobi: block still rotating
+    unsigned char *dsec = reinterpret_cast<unsigned char *>(jflag + 2);  // [L+1][2] bond sectors
     unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
 
     int total_sweeps = 0;
@@ -685,12 +836,11 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             __syncthreads();
             {
                 const long long t0 = wall_clock64();
-                const int wv = tid >> 6;
-                if (wv < 2) {
-                    const int sw = jacobi_block<T, MAXB>(Tm + wv * bst, Wm + wv * bst, ldt, wv ? K1 : K0, n, chi,
-                                                   tid & 63);
-                    if ((tid & 63) == 0) iflag[wv] = sw;
-                }
+                // waves 0, 1: blocks 0, 1; waves 2, 3: their rotations
+                const int wv = tid >> 6, pb = wv & 1;
+                const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
+                                                     tid & 63, wv >> 1, pb, jprm, jflag);
+                if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                 cyc_jac += wall_clock64() - t0;
