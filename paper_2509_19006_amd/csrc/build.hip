@@ -51,7 +51,8 @@ TNMC_LB(float, __half)
 size_t build_lds_bytes(int chi, int L, size_t tsize) {
     const size_t cb = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);
     const size_t regA = 7 * cb * cb;
-    const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi;
+    const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi +
+                        (cb <= 32 ? (size_t)4 * chi * chi : 0);   // + staged Q slot
     size_t elems = (regA > regS ? regA : regS);
     elems += 2 * cb + 2 * (chi + 2) + 4 * cb;                 // tau, nrm, Jacobi rotations
     size_t bytes = elems * tsize;

@@ -644,7 +644,10 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 
     // ---- shared memory layout (see build_lds_bytes) ----------------------
     const int regA_sz = 7 * CB * CB;                               // QR phase
-    const int regS_sz = 4 * bst + 2 * cc2;                         // SVD phase
+    // for chi <= 32 the SVD phase also holds the next site's Q slot, staged
+    // by waves 2 and 3 while waves 0 and 1 run the Jacobi
+    const bool qstage = CB <= 32;
+    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 : 0);  // SVD phase
     T *reg = reinterpret_cast<T *>(smem);
     T *C = reg;                       // [CB][CB]
     T *R = reg + CB * CB;             // [2][CB][CB]
@@ -652,6 +655,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     T *Tm = reg;                      // [2][chi+1][ldt]
     T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
     T *X = reg + 4 * bst;             // [2][chi][chi]
+    T *Qst = X + 2 * cc2;             // [2][2chi][chi] staged Q slot (chi <= 32)
     T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
     T *tau = tail;                    // [2][CB]
     T *nrm = tau + 2 * CB;            // [2][chi+2]
@@ -775,16 +779,26 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             if (c == 0) {
                 // site 0: one row (even), columns (s=0, m even) and (s=1, m odd)
                 double sp = 0.0;
-                for (int m = tid; m < kr; m += NT) {
-                    const int p = (m >= r0);                    // sector of m; physical s = p
-                    const int mm = p ? m - r0 : m;
-                    const int mcq = mq[2 * (c + 1) + p];        // QR bond c|c+1 sector p
-                    const T *qrow = q + p * 2 * cc2;            // Q^p, sigma = p part starts at row 0
-                    T acc = 0;
-                    for (int j = 0; j < mcq; ++j) acc += qrow[j] * X[p * cc2 + j * chi + mm];
-                    nrm[m] = acc;
-                    sp += (double)acc * (double)acc;
-                }
+                auto row0 = [&](const T *qsrc) {
+                    for (int m = tid; m < kr; m += NT) {
+                        const int p = (m >= r0);                    // sector of m; physical s = p
+                        const int mm = p ? m - r0 : m;
+                        const int mcq = mq[2 * (c + 1) + p];        // QR bond c|c+1 sector p
+                        const T *qrow = qsrc + p * 2 * cc2;         // Q^p, sigma = p part starts at row 0
+                        const T *xc = X + p * cc2 + mm;
+                        T acc = 0, a1 = 0;
+                        int j = 0;
+                        for (; j + 1 < mcq; j += 2) {
+                            acc += qrow[j] * xc[j * chi];
+                            a1 += qrow[j + 1] * xc[(j + 1) * chi];
+                        }
+                        if (j < mcq) acc += qrow[j] * xc[j * chi];
+                        acc += a1;
+                        nrm[m] = acc;
+                        sp += (double)acc * (double)acc;
+                    }
+                };
+                if (qstage) row0(Qst); else row0(q);
                 const double n0 = sqrt(block_sum(sp, red));
                 ls += log(n0);
                 const T inv = (T)(1.0 / n0);
@@ -815,6 +829,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             } else {
                 const int mn0 = mq[2 * (c + 1)], mn1 = mq[2 * (c + 1) + 1];   // QR bond c|c+1 sectors
                 // idx fastest: neighbouring threads share rows of Q
+                auto tform = [&](const T *qsrc) {
                 for (int e = tid; e < 2 * n * chi; e += NT) {
                     const int p = e / (n * chi), k = (e / n) % chi, idx = e % n;
                     const int Kp = p ? K1 : K0;
@@ -826,12 +841,24 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                         const int qb = s1 ? 1 - p : p, xb = qb, xc = s1 ? idx - dp : idx;
                         const int rowoff = s1 ? (qb == 0 ? K0 : K1) : 0;
                         const int mcq = xb ? mn1 : mn0;
-                        const T *qr = q + qb * 2 * cc2 + (rowoff + k) * chi;
+                        const T *qr = qsrc + qb * 2 * cc2 + (rowoff + k) * chi;
                         const T *xr = X + xb * cc2 + xc;
-                        for (int j = 0; j < mcq; ++j) acc += qr[j] * xr[j * chi];
+                        // four partial sums: independent chains hide the LDS latency
+                        T a1 = 0, a2 = 0, a3 = 0;
+                        int j = 0;
+                        for (; j + 3 < mcq; j += 4) {
+                            acc += qr[j] * xr[j * chi];
+                            a1 += qr[j + 1] * xr[(j + 1) * chi];
+                            a2 += qr[j + 2] * xr[(j + 2) * chi];
+                            a3 += qr[j + 3] * xr[(j + 3) * chi];
+                        }
+                        for (; j < mcq; ++j) acc += qr[j] * xr[j * chi];
+                        acc = (acc + a1) + (a2 + a3);
                     }
                     Tm[p * bst + idx * ldt + k] = acc;
                 }
+                };
+                if (qstage) tform(Qst); else tform(q);
             }
             __syncthreads();
             {
@@ -841,6 +868,11 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
                                                      tid & 63, wv >> 1, pb, jprm, jflag);
                 if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
+                if (qstage && wv >= 2) {
+                    // meanwhile: the next site's Q slot into shared memory
+                    const T *src = qscr + (size_t)(c - 1) * 4 * cc2;
+                    for (int e = tid - 128; e < 4 * cc2; e += 128) Qst[e] = src[e];
+                }
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                 cyc_jac += wall_clock64() - t0;
@@ -848,34 +880,43 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             // singular values of both blocks (padding columns and empty blocks excluded)
             for (int e = tid; e < 2 * n; e += NT) {
                 const int p = e / n, col = e % n, Kp = p ? K1 : K0;
-                T s2 = 0;
-                if (col < kr) for (int k = 0; k < Kp; ++k) { const T v = Tm[p * bst + col * ldt + k]; s2 += v * v; }
-                nrm[e] = (col < kr && Kp > 0) ? sqrt(s2) : (T)-1;
+                const T *cp = Tm + p * bst + col * ldt;
+                T s2 = 0, s3 = 0;
+                if (col < kr) {
+                    int k = 0;
+                    for (; k + 1 < Kp; k += 2) { s2 += cp[k] * cp[k]; s3 += cp[k + 1] * cp[k + 1]; }
+                    if (k < Kp) s2 += cp[k] * cp[k];
+                }
+                nrm[e] = (col < kr && Kp > 0) ? sqrt(s2 + s3) : (T)-1;
             }
             __syncthreads();
             int kk = chi < K0 + K1 ? chi : K0 + K1;
             if (2 * kr < kk) kk = 2 * kr;
+            // rank of every column over both blocks (ties by index); 2n is a
+            // multiple of 4
             for (int e = tid; e < 2 * n; e += NT) {
                 const T v = nrm[e];
-                int rk = 0;
-                for (int o = 0; o < 2 * n; ++o) { const T w = nrm[o]; rk += (w > v) || (w == v && o < e); }
-                rankv[e] = (v >= (T)0) ? rk : 1 << 20;
+                int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+                for (int o = 0; o < 2 * n; o += 4) {
+                    const T w0 = nrm[o], w1 = nrm[o + 1], w2 = nrm[o + 2], w3 = nrm[o + 3];
+                    q0 += (w0 > v) || (w0 == v && o < e);
+                    q1 += (w1 > v) || (w1 == v && o + 1 < e);
+                    q2 += (w2 > v) || (w2 == v && o + 2 < e);
+                    q3 += (w3 > v) || (w3 == v && o + 3 < e);
+                }
+                rankv[e] = (v >= (T)0) ? (q0 + q1) + (q2 + q3) : 1 << 20;
             }
             __syncthreads();
             // new left bond: kept columns of block 0 (by rank), then of block 1
-            if (tid == 0) {
-                int s0 = 0, s1 = 0;
-                for (int e = 0; e < 2 * n; ++e) if (rankv[e] < kk) { if (e < n) ++s0; else ++s1; }
-                iflag[1] = s0; iflag[2] = s1;
-            }
-            __syncthreads();
-            const int s0 = iflag[1];
+            // (2n <= 128 < NT: one column per thread)
+            const int s0 = __syncthreads_count(tid < n && rankv[tid] < kk);
             for (int e = tid; e < 2 * n; e += NT) {
                 if (rankv[e] < kk) {
-                    const int p = e / n;
-                    int pos = 0;
-                    for (int o = p * n; o < p * n + n; ++o) pos += rankv[o] < rankv[e];
-                    colof[(p ? s0 : 0) + pos] = e;
+                    const int p = e / n, re = rankv[e];
+                    const int *rb = rankv + p * n;
+                    int q0 = 0, q1 = 0;
+                    for (int o = 0; o < n; o += 2) { q0 += rb[o] < re; q1 += rb[o + 1] < re; }
+                    colof[(p ? s0 : 0) + q0 + q1] = e;
                 }
             }
             double kp = 0.0;
