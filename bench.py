@@ -214,6 +214,92 @@ def run_uneven(args):
     print(json.dumps(line), flush=True)
 
 
+def run_learned(args):
+    """Learned-correction form: a chi = 16 proposal whose per-site logits are
+    corrected by the MLP, trained on the GPU on chi = 64 conditionals of 16
+    separately seeded 256 x 256 Gaussian disorders (one trajectory each,
+    about 10^6 sites, spin-flip augmented), against the plain chi = 16 and
+    chi = 32 proposals on 1024 x 1024 Gaussian disorders at beta = 1."""
+    import numpy as np
+    import torch
+    import paper_2509_19006_amd as T
+    from paper_2509_19006_amd import learned
+    import workloads
+    T.load()
+    beta, Lt, L, B, N, B32 = 1.0, args.train_L, args.L, args.disorders, args.samples, args.disorders_chi32
+    t0 = time.time()
+    train_J = [workloads.instance(Lt, "gauss", 50, i) for i in range(16)]
+    log(f"training data: 16 disorders of {Lt}x{Lt}, chi 16 scored on chi 64 draws ...")
+    feat, lo, tgt = learned.make_training_data(train_J, 16, 64, beta, 1, seed=5)
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    log(f"  {lo.numel()} rows in {t_data:.1f} s; training {args.train_steps} Adam steps ...")
+    t1 = time.time()
+    P, losses = learned.train(feat, lo, tgt, steps=args.train_steps, batch=8192, lr=1e-3, seed=1, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    del feat, lo, tgt
+    torch.cuda.empty_cache()
+
+    def form(chi, nb, mlps):
+        Js = [workloads.instance(L, "gauss", 5, i) for i in range(nb)]
+        jh = torch.as_tensor(np.concatenate([a.ravel() for a, _ in Js])).cuda()
+        jv = torch.as_tensor(np.concatenate([b.ravel() for _, b in Js])).cuda()
+        p = T.Problem(jh, jv, [L] * nb, chi, beta)
+        ws = torch.empty(T.tnmc_workspace_size(p, T.FP32, N), dtype=torch.uint8, device="cuda")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        env = T.tnmc_build_env(p, T.FP32, ws)
+        ev[1].record()
+        torch.cuda.synchronize()
+        build_s = ev[0].elapsed_time(ev[1]) / 1e3
+        out = {}
+        for name, m in mlps:
+            spins = torch.empty(N * p.spin_words_per_sample(), dtype=torch.int64, device="cuda")
+            logq = torch.empty((nb, N), dtype=torch.float64, device="cuda")
+            E = torch.empty((nb, N), dtype=torch.float64, device="cuda")
+            acc = torch.empty((nb, N), dtype=torch.uint8, device="cuda")
+            chain = torch.zeros(nb * T.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
+            bt = torch.full((nb,), beta, dtype=torch.float64, device="cuda")
+            e2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e2[0].record()
+            T.tnmc_sample(env, N, 0x5A5A0005, spins, logq, mlp=m)
+            T.tnmc_energy(env, N, spins, E)
+            T.tnmc_accept(logq, E, bt, chain, 0x5A5A0005, 0, acc)
+            e2[1].record()
+            torch.cuda.synchronize()
+            st = T.chain_state(chain.cpu().numpy())
+            na = sum(c["n_acc"] for c in st)
+            nt = sum(c["n_trials"] for c in st)
+            samp_s = e2[0].elapsed_time(e2[1]) / 1e3
+            out[name] = {"chi": chi, "disorders": nb, "acceptance": na / max(1, nt), "accepted": na, "trials": nt,
+                         "build_s": build_s, "sample_energy_accept_s": samp_s,
+                         "accepted_per_s": na / (build_s + samp_s)}
+            log(f"  {name}: acceptance {na / max(1, nt):.4f}, build {build_s:.1f} s, sampling {samp_s:.2f} s")
+        del ws, env
+        torch.cuda.empty_cache()
+        return out
+
+    log(f"evaluation: {B} Gaussian disorders of {L}x{L}, {N} samples, beta {beta}")
+    res = form(16, B, [("plain chi16", None), ("learned chi16+mlp", P)])
+    log(f"plain chi 32 on {B32} of the disorders ...")
+    res.update(form(32, B32, [("plain chi32", None)]))
+    lr = res["learned chi16+mlp"]
+    line = {
+        "metric": "accepted samples/s + acceptance rate, learned correction vs plain",
+        "value": lr["accepted_per_s"], "unit": "accepted samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": (lr["build_s"] + lr["sample_energy_accept_s"]) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"learned-correction TNMC: {L}x{L} Gaussian lattices, beta 1, {B} disorders x {N} "
+                               f"samples; chi 16 + 3-layer MLP (width 64, bf16 weights) trained on chi 64 "
+                               f"conditionals of 16 separately seeded {Lt}x{Lt} disorders"},
+        "forms": res,
+        "training": {"rows": int(2 * 16 * Lt * Lt), "data_s": t_data, "train_s": t_train,
+                     "steps": args.train_steps, "loss_first_last": [losses[0][1], losses[-1][1]]},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,9 +313,13 @@ def main():
     ap.add_argument("--mixed", choices=["bf16", "fp16"], default="fp16")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain float32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["mixed", "uneven"], default="mixed",
+    ap.add_argument("--workload", choices=["mixed", "uneven", "learned"], default="mixed",
                     help="mixed: the headline 256x256 batch (default); uneven: the 512-instance mix in one "
-                         "persistent launch with an autotuned schedule")
+                         "persistent launch with an autotuned schedule; learned: the learned correction "
+                         "(use with --L 1024 --disorders 64 --samples 16)")
+    ap.add_argument("--train-L", type=int, default=256, help="learned: side of the training lattices")
+    ap.add_argument("--train-steps", type=int, default=1500, help="learned: Adam steps")
+    ap.add_argument("--disorders-chi32", type=int, default=16, help="learned: disorders of the chi 32 comparison")
     ap.add_argument("--objective", choices=["p99", "p50", "mean", "makespan"], default="p99",
                     help="what the schedule autotuner minimises (uneven workload)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
@@ -254,6 +344,9 @@ def main():
         return
     if args.workload == "uneven":
         run_uneven(args)
+        return
+    if args.workload == "learned":
+        run_learned(args)
         return
     import paper_2509_19006_amd as T
     import workloads
