@@ -176,14 +176,48 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
     constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
     int g = lane / G, gl = lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
+    // Start from the columns ordered by decreasing norm (de Rijk's
+    // pivoting, which shortens cyclic Jacobi): lane l < CHI measures column
+    // l, ranks it among all, and position p takes the column of rank p.
+    // Positions, not column numbers, are written back: the caller ranks the
+    // result by norm, and W's columns follow the block's.
+    int src2, src3;
+    {
+        T nl = (T)-1;
+        if (lane < n) {
+            T q0 = 0, q1 = 0;
+            const T *cp = Tb + lane * ld;
+            T q2 = 0, q3 = 0;
+            int k = 0;
+            for (; k + 3 < K; k += 4) {
+                q0 += cp[k] * cp[k];
+                q1 += cp[k + 1] * cp[k + 1];
+                q2 += cp[k + 2] * cp[k + 2];
+                q3 += cp[k + 3] * cp[k + 3];
+            }
+            for (; k < K; ++k) q0 += cp[k] * cp[k];
+            nl = (q0 + q1) + (q2 + q3);
+        }
+        int rk = 0;
+#pragma unroll
+        for (int j = 0; j < CHI; ++j) {
+            const T nj = bperm<T>(j << 2, nl);
+            rk += (nj > nl) || (nj == nl && j < lane);
+        }
+        // column of each position: lane l sends its index to lane rank(l)
+        const int colpos = __builtin_amdgcn_ds_permute((lane < CHI ? rk : lane) << 2, lane);
+        // (clamped: a position nobody claimed reads as padding)
+        src2 = (int)min((unsigned)__builtin_amdgcn_ds_bpermute((2 * g) << 2, colpos), (unsigned)CHI);
+        src3 = (int)min((unsigned)__builtin_amdgcn_ds_bpermute((2 * g + 1) << 2, colpos), (unsigned)CHI);
+    }
     T x[RK], y[RK], wx[RK], wy[RK];
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
-        x[i] = (row < K && 2 * g < n) ? Tb[(2 * g) * ld + row] : (T)0;
-        y[i] = (row < K && 2 * g + 1 < n) ? Tb[(2 * g + 1) * ld + row] : (T)0;
-        wx[i] = (row == 2 * g) ? (T)1 : (T)0;
-        wy[i] = (row == 2 * g + 1) ? (T)1 : (T)0;
+        x[i] = (row < K && src2 < n) ? Tb[src2 * ld + row] : (T)0;
+        y[i] = (row < K && src3 < n) ? Tb[src3 * ld + row] : (T)0;
+        wx[i] = (row == src2) ? (T)1 : (T)0;
+        wy[i] = (row == src3) ? (T)1 : (T)0;
     }
     const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
     const bool last = (g == HP - 1);
