@@ -198,3 +198,24 @@ def test_c1_exact_regime_accepts_everything(G, tnmc):
     assert acc.all()
     st = tnmc.chain_state(chain.cpu().numpy())
     assert all(s["n_acc"] == n - 1 and s["n_trials"] == n - 1 for s in st)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_degenerate_weights_give_the_uniform_law(G, tnmc, prec):
+    """beta = 0, or every coupling zero: every configuration has weight 1, so
+    ln Z = L^2 ln 2 and every draw has log q = -L^2 ln 2 at any chi; the
+    chain accepts everything."""
+    L, chi, n = 12, 4, 40
+    Js = [workloads.instance(L, "gauss", 43, 0), workloads.instance(L, "pmj", 43, 1)]
+    zero = (np.zeros((L, L - 1), np.float32), np.zeros((L - 1, L), np.float32))
+    want = -L * L * math.log(2.0)
+    tol = TOL[prec]
+    for beta, inst in ((0.0, Js), (1.0, [zero, zero])):
+        G.say(f"degenerate: beta {beta}, prec {prec}")
+        run = G.Run(inst, chi, beta, prec, max_samples=n)
+        sp, lq, _ = run.sample(n, seed=3)
+        assert np.max(rel_err(run.logz, -want)) < tol
+        assert np.max(rel_err(lq, want)) < tol
+        acc, _, _ = G.gpu_accept(lq, run.energy(sp), np.full(len(inst), beta), 3, 0)
+        if beta == 0.0:
+            assert acc.all()
