@@ -100,6 +100,12 @@ __device__ __forceinline__ int seat(int q, int t, int n) {
 
 __device__ __forceinline__ double fast_rcp(double x) { return __builtin_amdgcn_rcp(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Square root on the rotation's critical path: the hardware's 1-ulp float
+// instruction (the correctly rounded sequence is about ten times longer; it
+// differs only for denormal inputs, which the caller excludes); float64
+// keeps the exact operation.
+__device__ __forceinline__ double path_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float path_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 // 1/sqrt(x) from the hardware estimate refined by one Newton step.
 __device__ __forceinline__ double rsqrt_nr(double x) {
     const double y = __builtin_amdgcn_rsq(x);
@@ -139,9 +145,9 @@ template <> __device__ __forceinline__ double bperm<double>(int addr, double v) 
 // tolerance or either column is noise.  Returns whether it rotates.
 template <typename T>
 __device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, bool live, T &cs, T &sn, T &tt) {
-    const bool ok = live && a > small && b > small && c * c > tol2 * a * b;
     const T d = b - a, e = c + c;
-    const T den = fabs(d) + sqrt(d * d + e * e);
+    const T den = fabs(d) + path_sqrt(d * d + e * e);
+    const bool ok = live && a > small && b > small && c * c > tol2 * a * b && den > (T)0;
     const T t = (d >= 0 ? e : -e) * fast_rcp(ok ? den : (T)1);
     const T c0 = rsqrt_nr((T)1 + t * t);
     tt = ok ? t : (T)0;
