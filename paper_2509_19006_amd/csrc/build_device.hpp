@@ -115,6 +115,10 @@ __device__ __forceinline__ float rsqrt_nr(float x) {
     const float y = __builtin_amdgcn_rsqf(x);
     return y * (1.5f - 0.5f * x * y * y);
 }
+// 1/sqrt on the rotation's dependency chain: the float estimate is already
+// within an ulp; float64 needs the Newton step.
+__device__ __forceinline__ double path_rsqrt(double x) { return rsqrt_nr(x); }
+__device__ __forceinline__ float path_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Orders a wave's shared-memory accesses without a workgroup barrier: the
 // LDS serves one wave's instructions in order, the fences stop the compiler
@@ -149,7 +153,7 @@ __device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, 
     const T den = fabs(d) + path_sqrt(d * d + e * e);
     const bool ok = live && a > small && b > small && c * c > tol2 * a * b && den > (T)0;
     const T t = (d >= 0 ? e : -e) * fast_rcp(ok ? den : (T)1);
-    const T c0 = rsqrt_nr((T)1 + t * t);
+    const T c0 = path_rsqrt((T)1 + t * t);
     tt = ok ? t : (T)0;
     cs = ok ? c0 : (T)1;
     sn = ok ? c0 * t : (T)0;
