@@ -39,6 +39,9 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                             const uint64_t *__restrict__ forced, uint64_t *spins_out,
                             double *__restrict__ logq_out, float *__restrict__ logits_out,
                             const float *__restrict__ Jv_all, MlpArgs mlp, T (*As)[CHI][CHI], float *Ps) {
+    // no implicit multiply-add fusion: the sampler gives the same bits in
+    // every kernel it is inlined into; the contractions fuse explicitly
+#pragma clang fp contract(off)
     const int tid = threadIdx.x;
     const int n = tile * NTS + tid;
     const bool act = n < n_samples;
@@ -58,10 +61,27 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
         // weights rounded to bfloat16 (float32 accumulation)
         for (int e = tid; e < MLP_NPARAM; e += NTS) Ps[e] = __bfloat162float(__float2bfloat16(mlp.params[e]));
     }
-    auto stage = [&](const S *site) {
-        for (int e = tid; e < 2 * CHI * CHI; e += NTS) {
+    // Sites are staged through two shared buffers: the next site's entries
+    // are fetched into registers before the current site is contracted and
+    // stored into the other buffer after it, so one barrier per site
+    // suffices and the fetch latency hides behind the contraction.
+    constexpr int PER = (2 * CHI * CHI + NTS - 1) / NTS;
+    T pre[PER];
+    auto fetch = [&](const S *site) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + i * NTS;
             const int s = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
-            As[s][a][b] = (a < chi && b < chi) ? load_as<T, S>(site + (size_t)s * chi * chi + a * chi + b) : (T)0;
+            pre[i] = (e < 2 * CHI * CHI && a < chi && b < chi)
+                         ? load_as<T, S>(site + (size_t)s * chi * chi + a * chi + b) : (T)0;
+        }
+    };
+    auto put = [&](int buf) {
+        T *dst = &As[2 * buf][0][0];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + i * NTS;
+            if (e < 2 * CHI * CHI) dst[e] = pre[i];
         }
     };
 
@@ -75,11 +95,17 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
             for (int a = 0; a < CHI; ++a) R[a] = (a == 0) ? (T)1 : (T)0;
             int uw_idx = -1;
             uint64_t uw = 0;
+            int buf = 0;
+            if (L >= 2) {
+                fetch(crow + (size_t)(L - 1) * site_sz);
+                put(0);
+            }
+            __syncthreads();
             for (int c = L - 2; c >= 0; --c) {
-                __syncthreads();
-                stage(crow + (size_t)(c + 1) * site_sz);
-                __syncthreads();
-                if (!act) continue;
+                const bool more = c > 0;
+                if (more) fetch(crow + (size_t)c * site_sz);
+                T (*Ab)[CHI][CHI] = As + 2 * buf;
+                if (act) {
                 T w0 = 1, w1 = 1;
                 if (r > 0) {
                     const int cc = c + 1, wi = cc >> 6;
@@ -96,8 +122,8 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 for (int a = 0; a < CHI; ++a) {
                     T z0 = 0, z1 = 0;
 #pragma unroll
-                    for (int b = 0; b < CHI; ++b) { z0 += As[0][a][b] * R[b]; z1 += As[1][a][b] * R[b]; }
-                    Rn[a] = w0 * z0 + w1 * z1;
+                    for (int b = 0; b < CHI; ++b) { z0 = fma(Ab[0][a][b], R[b], z0); z1 = fma(Ab[1][a][b], R[b], z1); }
+                    Rn[a] = fma(w0, z0, w1 * z1);
                     mx = fmax(mx, fabs(Rn[a]));
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -105,6 +131,11 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 T *ec = env + (size_t)c * CHI * NTS + tid;
 #pragma unroll
                 for (int a = 0; a < CHI; ++a) { R[a] = Rn[a] * sc; ec[(size_t)a * NTS] = R[a]; }
+                }
+                // one barrier site that every thread reaches
+                if (more) put(buf ^ 1);
+                __syncthreads();
+                buf ^= 1;
             }
         }
         // ---------------- left sweep: sample the row ----------------
@@ -113,11 +144,15 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
 #pragma unroll
             for (int a = 0; a < CHI; ++a) l[a] = (a == 0) ? (T)1 : (T)0;
             uint64_t cur = 0, up = 0, fw = 0;
+            int buf = 0;
+            fetch(crow);
+            put(0);
+            __syncthreads();
             for (int c = 0; c < L; ++c) {
-                __syncthreads();
-                stage(crow + (size_t)c * site_sz);
-                __syncthreads();
-                if (!act) continue;
+                const bool more = c + 1 < L;
+                if (more) fetch(crow + (size_t)(c + 1) * site_sz);
+                T (*Ab)[CHI][CHI] = As + 2 * buf;
+                if (act) {
                 // y_s = l A_{c,s} for both spins; every staged value is read once
                 T y0[CHI], y1[CHI];
 #pragma unroll
@@ -126,7 +161,7 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 for (int a = 0; a < CHI; ++a) {
                     const T la = l[a];
 #pragma unroll
-                    for (int b = 0; b < CHI; ++b) { y0[b] += la * As[0][a][b]; y1[b] += la * As[1][a][b]; }
+                    for (int b = 0; b < CHI; ++b) { y0[b] = fma(la, Ab[0][a][b], y0[b]); y1[b] = fma(la, Ab[1][a][b], y1[b]); }
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 // rho_s = y_s . R_c  (R_{L-1} = e_0)
@@ -137,7 +172,7 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                     const T *ec = env + (size_t)c * CHI * NTS + tid;
                     r0 = 0; r1 = 0;
 #pragma unroll
-                    for (int b = 0; b < CHI; ++b) { const T rb = ec[(size_t)b * NTS]; r0 += y0[b] * rb; r1 += y1[b] * rb; }
+                    for (int b = 0; b < CHI; ++b) { const T rb = ec[(size_t)b * NTS]; r0 = fma(y0[b], rb, r0); r1 = fma(y1[b], rb, r1); }
                 }
                 const double rho0 = fabs((double)r0), rho1 = fabs((double)r1);
                 double logit = 0.0;
@@ -146,7 +181,7 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                     if (my_forced) fw = my_forced[(size_t)r * W + (c >> 6)];
                 }
                 if (rho0 > 0.0 || rho1 > 0.0) {
-                    logit = log(rho1) - log(rho0);
+                    logit = log(rho1 / rho0);
                     if (r > 0) {
                         const double u = (double)((up >> (c & 63)) & 1);
                         logit += 2.0 * beta * (double)jv[(size_t)(r - 1) * L + c] * (2.0 * u - 1.0);
@@ -166,15 +201,20 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                     mlp_features(jh, jv, L, r, c, spin, (float)logit, x);
                     logit += (double)mlp_forward(Ps, x);
                 }
+                // sigma(logit) and ln sigma(+-logit) from one exponential:
+                // with e = exp(-|logit|), sigma = 1/(1+e) or e/(1+e) and
+                // ln sigma(x) = min(x, 0) - ln(1 + e)
+                const double ex = exp(-fabs(logit));
+                const double l1p = log1p(ex);
                 int spin;
                 if (my_forced) {
                     spin = (int)((fw >> (c & 63)) & 1);
                 } else {
-                    const double p = 1.0 / (1.0 + exp(-logit));
+                    const double p = (logit >= 0.0 ? 1.0 : ex) / (1.0 + ex);
                     const double u = philox_unit(seed, (uint32_t)(r * L + c), sidx, (uint32_t)inst, 0u);
                     spin = (u < p) ? 1 : 0;
                 }
-                logq += spin ? log_sigmoid(logit) : log_sigmoid(-logit);
+                logq += (spin ? fmin(logit, 0.0) : fmin(-logit, 0.0)) - l1p;
                 if (my_logits) my_logits[(size_t)r * L + c] = (float)logit;
                 cur |= (uint64_t)spin << (c & 63);
                 if ((c & 63) == 63 || c == L - 1) { my_out[(size_t)r * W + (c >> 6)] = cur; cur = 0; }
@@ -187,6 +227,11 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 const T sc = mx > (T)0 ? pow2_inv(mx) : (T)1;
 #pragma unroll
                 for (int b = 0; b < CHI; ++b) l[b] = ln[b] * sc;
+                }
+                // one barrier site that every thread reaches
+                if (more) put(buf ^ 1);
+                __syncthreads();
+                buf ^= 1;
             }
         }
     }
