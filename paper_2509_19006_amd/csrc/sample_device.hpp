@@ -65,15 +65,18 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
     // are fetched into registers before the current site is contracted and
     // stored into the other buffer after it, so one barrier per site
     // suffices and the fetch latency hides behind the contraction.
+    // (the raw stored values are held: converting them at fetch time would
+    // make the fetch wait for its loads before the contraction)
     constexpr int PER = (2 * CHI * CHI + NTS - 1) / NTS;
-    T pre[PER];
+    S pre[PER];
+    bool inb[PER];
     auto fetch = [&](const S *site) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + i * NTS;
             const int s = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
-            pre[i] = (e < 2 * CHI * CHI && a < chi && b < chi)
-                         ? load_as<T, S>(site + (size_t)s * chi * chi + a * chi + b) : (T)0;
+            inb[i] = e < 2 * CHI * CHI && a < chi && b < chi;
+            if (inb[i]) pre[i] = site[(size_t)s * chi * chi + a * chi + b];
         }
     };
     auto put = [&](int buf) {
@@ -81,7 +84,7 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + i * NTS;
-            if (e < 2 * CHI * CHI) dst[e] = pre[i];
+            if (e < 2 * CHI * CHI) dst[e] = inb[i] ? load_as<T, S>(&pre[i]) : (T)0;
         }
     };
 
