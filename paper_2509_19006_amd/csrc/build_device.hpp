@@ -145,18 +145,27 @@ template <> __device__ __forceinline__ double bperm<double>(int addr, double v) 
 // Rotation that makes columns with squared norms a, b and inner product c
 // orthogonal: with d = b - a and e = 2c, tan = sign(d) e / (|d| + sqrt(d^2 +
 // e^2)) (the smaller root of Rutishauser's quadratic, free of overflow for
-// |d| >> |e|); identity (cs = 1, sn = t = 0) when the pair is orthogonal to
-// tolerance or either column is noise.  Returns whether it rotates.
+// |d| >> |e|); identity (cs = 1, sn = 0) when the pair is orthogonal to
+// tolerance or either column is noise.  An idle pair (live false) gets the
+// exact quarter turn cs = 0, sn = 1, (u, v) -> (-v, u): it exchanges the two
+// columns (one negated, which the SVD does not see: the same column of W
+// changes sign with it), so that every group hands on its columns the same
+// way after the step.  Updates the squared norms (a' = a - t c, b' = b + t c;
+// exchanged for an idle pair) and returns whether the pair rotates.
 template <typename T>
-__device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, bool live, T &cs, T &sn, T &tt) {
+__device__ __forceinline__ bool jacobi_rotation(T &a, T &b, T c, T small, T tol2, bool live, T &cs, T &sn) {
     const T d = b - a, e = c + c;
     const T den = fabs(d) + path_sqrt(d * d + e * e);
-    const bool ok = live && a > small && b > small && c * c > tol2 * a * b && den > (T)0;
+    // (bitwise: a short-circuit chain becomes branches on the exec mask)
+    const bool ok = live & (a > small) & (b > small) & (c * c > tol2 * a * b) & (den > (T)0);
     const T t = (d >= 0 ? e : -e) * fast_rcp(ok ? den : (T)1);
     const T c0 = path_rsqrt((T)1 + t * t);
-    tt = ok ? t : (T)0;
-    cs = ok ? c0 : (T)1;
-    sn = ok ? c0 * t : (T)0;
+    const T tt = ok ? t : (T)0;
+    cs = ok ? c0 : (live ? (T)1 : (T)0);
+    sn = ok ? c0 * t : (live ? (T)0 : (T)1);
+    const T na = live ? a - tt * c : b, nb = live ? b + tt * c : a;
+    a = na;
+    b = nb;
     return ok;
 }
 
@@ -173,8 +182,9 @@ __device__ __forceinline__ bool jacobi_rotation(T a, T b, T c, T small, T tol2, 
 // over its lanes) for both the block and the accumulated rotation W.  Going
 // from an even to an odd step a group takes the second column of the next
 // group; going back, the first column of the previous group (the last group,
-// idle in odd steps, hands over its second): one move per column and step,
-// through the LDS permute crossbar.  Squared column norms are recomputed
+// idle in odd steps, exchanges its two by a quarter turn first, so it hands
+// over the one at position 0): one move per column and step, through the
+// LDS permute crossbar.  Squared column norms are recomputed
 // every sweep and carried through each rotation exactly (a' = a - t*g,
 // b' = b + t*g), so a pair needs one reduction.  Pairs whose smaller column
 // is below sqrt(n)*eps*||T||_F are left alone: such columns are rounding
@@ -253,8 +263,8 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
                     if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
                 }
                 const T c = group_sum(c0 + c1, G);
-                T cs, sn, tt;
-                rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn, tt);
+                T cs, sn;
+                rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
 #pragma unroll
                 for (int i = 0; i < RK; ++i) {
                     const T u = x[i], v = y[i];
@@ -264,8 +274,6 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
                     wx[i] = cs * p - sn * q;
                     wy[i] = sn * p + cs * q;
                 }
-                a -= tt * c;
-                b += tt * c;
                 if (!odd) {
                     // even -> odd layout: second column from the next group
 #pragma unroll
@@ -273,20 +281,10 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
                     b = bperm<T>(up, b);
                 } else {
                     // odd -> even layout: first column from the previous
-                    // group; the idle last group keeps its first as second
-                    // and hands over its second
+                    // group (the idle last group has exchanged its two)
 #pragma unroll
-                    for (int i = 0; i < RK; ++i) {
-                        const T sx = last ? y[i] : x[i], sw_ = last ? wy[i] : wx[i];
-                        const T nx = bperm<T>(dn, sx), nw = bperm<T>(dn, sw_);
-                        y[i] = last ? x[i] : y[i];
-                        wy[i] = last ? wx[i] : wy[i];
-                        x[i] = nx;
-                        wx[i] = nw;
-                    }
-                    const T na = bperm<T>(dn, last ? b : a);
-                    b = last ? a : b;
-                    a = na;
+                    for (int i = 0; i < RK; ++i) { x[i] = bperm<T>(dn, x[i]); wx[i] = bperm<T>(dn, wx[i]); }
+                    a = bperm<T>(dn, a);
                 }
             }
         }
@@ -325,8 +323,9 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
 // columns of its pair (rows strided over its lanes).  Going from an even to
 // an odd step a group takes the second column of the next group; going
 // back, the first column of the previous group (the last group, idle in odd
-// steps, hands over its second): one move per column and step, through the
-// LDS permute crossbar.
+// steps, exchanges its two by a quarter turn first, so it hands over the one
+// at position 0): one move per column and step, through the LDS permute
+// crossbar.
 //   role 0 (the block): squared column norms are recomputed every sweep and
 //   carried through each rotation exactly (a' = a - t*g, b' = b + t*g), so a
 //   pair needs one reduction; pairs whose smaller column is below
@@ -389,11 +388,8 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
                         if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
                     }
                     const T c = group_sum(c0 + c1, G);
-                    T tt;
-                    rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn, tt);
+                    rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
                     if (gl == 0) { ps[0] = cs; ps[1] = sn; }
-                    a -= tt * c;
-                    b += tt * c;
                 }
                 __syncthreads();
                 if (!blk) {
@@ -414,19 +410,10 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
                     if (blk) b = bperm<T>(up, b);
                 } else {
                     // odd -> even layout: first column from the previous
-                    // group; the idle last group keeps its first as second
-                    // and hands over its second
+                    // group (the idle last group has exchanged its two)
 #pragma unroll
-                    for (int i = 0; i < RK; ++i) {
-                        const T nx = bperm<T>(dn, last ? y[i] : x[i]);
-                        y[i] = last ? x[i] : y[i];
-                        x[i] = nx;
-                    }
-                    if (blk) {
-                        const T na = bperm<T>(dn, last ? b : a);
-                        b = last ? a : b;
-                        a = na;
-                    }
+                    for (int i = 0; i < RK; ++i) x[i] = bperm<T>(dn, x[i]);
+                    if (blk) a = bperm<T>(dn, a);
                 }
             }
         }
