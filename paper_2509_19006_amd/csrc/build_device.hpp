@@ -142,6 +142,24 @@ template <> __device__ __forceinline__ double bperm<double>(int addr, double v) 
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Shared-memory accesses through the LDS address space (plain ds
+// instructions, no flat access and no wait after a store).  Two waves hand
+// data over with them in program order: the LDS unit serves one wave's
+// instructions in the order issued, so the only ordering to enforce is the
+// compiler's (lds_order).  lds_poll reads a word another wave writes, anew
+// on every call.
+template <typename U> __device__ __forceinline__ void lds_put(U *p, U v) {
+    *(__attribute__((address_space(3))) U *)p = v;
+}
+template <typename U> __device__ __forceinline__ U lds_get(const U *p) {
+    return *(const __attribute__((address_space(3))) U *)p;
+}
+__device__ __forceinline__ int lds_poll(const int *p) {
+    return __hip_atomic_load((const __attribute__((address_space(3))) int *)p, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
 // Rotation that makes columns with squared norms a, b and inner product c
 // orthogonal: with d = b - a and e = 2c, tan = sign(d) e / (|d| + sqrt(d^2 +
 // e^2)) (the smaller root of Rutishauser's quadratic, free of overflow for
@@ -169,44 +187,107 @@ __device__ __forceinline__ bool jacobi_rotation(T &a, T &b, T c, T small, T tol2
     return ok;
 }
 
-// One-sided (Hestenes) Jacobi on one block, run by a single wave with the
-// block and its accumulated rotation W in registers (the form for chi <= 32,
-// where a step is bound by its dependency chain, not by issue).  The block has n columns (n even, n <= CHI) of length
-// K <= CHI at Tb, column-major with leading dimension ld; columns n..CHI-1
-// are treated as zero and never rotate.  Column pairs follow the odd-even
-// transposition order over CHI positions: even steps pair positions
-// (2g, 2g+1), odd steps (2g+1, 2g+2) with positions 0 and CHI-1 idle, and
-// every pair swaps positions after its step; CHI steps meet every pair once
-// and reverse the order.  The wave splits into CHI/2 lane groups of
-// G = 128/CHI lanes; group g holds the two columns of its pair (rows strided
-// over its lanes) for both the block and the accumulated rotation W.  Going
-// from an even to an odd step a group takes the second column of the next
-// group; going back, the first column of the previous group (the last group,
-// idle in odd steps, exchanges its two by a quarter turn first, so it hands
-// over the one at position 0): one move per column and step, through the
-// LDS permute crossbar.  Squared column norms are recomputed
-// every sweep and carried through each rotation exactly (a' = a - t*g,
-// b' = b + t*g), so a pair needs one reduction.  Pairs whose smaller column
-// is below sqrt(n)*eps*||T||_F are left alone: such columns are rounding
-// noise and a relative orthogonality test on them never settles.  On return
-// the rotated block is back at Tb and W (n x n, same leading dimension) at
-// Wb.  Returns the sweep count.
-template <typename T, int CHI>
-__device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
-    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
-    int g = lane / G, gl = lane % G;
+// Lane groups of the register Jacobi.  In the contiguous layout group g is
+// lanes [gG, gG+G) and a column moves to the neighbouring group through the
+// LDS permute crossbar.  In the interleaved layout (CHI = 32, G = 4) group g
+// is lanes g, g+16, g+32, g+48: neighbouring groups are neighbouring lanes of
+// every 16-lane row, so a column moves by one DPP rotate of the row, and a
+// group's sum crosses the rows with the swaps of lane halves (l ^ 16, l ^ 32)
+// that gfx950 has.  Both keep a move or a sum inside the vector unit's
+// latency instead of an LDS round trip on the rotation's dependency chain.
+__device__ __forceinline__ float swap_sum16(float v) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);   // {own, partner} in either order
+}
+__device__ __forceinline__ float swap_sum32(float v) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ double swap_sum16(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ double swap_sum32(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+template <bool IL, typename T> __device__ __forceinline__ T pair_sum(T v, int G) {
+    if constexpr (IL) return swap_sum32(swap_sum16(v));
+    else return group_sum(v, G);
+}
+// value of the same lane slot in group g+1 (up) or g-1 (down), cyclically
+template <bool IL, typename T> __device__ __forceinline__ T from_next(T v, int up) {
+    if constexpr (IL) return dpp_move<0x12F>(v);   // row_ror:15
+    else return bperm<T>(up, v);
+}
+template <bool IL, typename T> __device__ __forceinline__ T from_prev(T v, int dn) {
+    if constexpr (IL) return dpp_move<0x121>(v);   // row_ror:1
+    else return bperm<T>(dn, v);
+}
+
+// One-sided (Hestenes) Jacobi on one block, the form for chi <= 32, with
+// the block in one wave's registers (role 0).  The block has n columns (n
+// even, n <= CHI) of length K <= CHI at Tb, column-major with leading
+// dimension ld; columns n..CHI-1 are treated as zero and never rotate.
+// Column pairs follow the odd-even transposition order over CHI positions:
+// even steps pair positions (2g, 2g+1), odd steps (2g+1, 2g+2) with
+// positions 0 and CHI-1 idle, and every pair swaps positions after its step;
+// CHI steps meet every pair once and reverse the order.  The wave splits
+// into CHI/2 lane groups of G = 128/CHI lanes (contiguous or interleaved,
+// IL); group g holds the two columns of its pair (rows strided over its
+// lanes).  Going from an even to an odd step a group takes the second column
+// of the next group; going back, the first column of the previous group (the
+// last group, idle in odd steps, exchanges its two by a quarter turn first,
+// so it hands over the one at position 0): one move per column and step.
+// Squared column norms are recomputed every sweep and carried through each
+// rotation exactly (a' = a - t*g, b' = b + t*g), so a pair needs one
+// reduction.  Pairs whose smaller column is below sqrt(n)*eps*||T||_F are
+// left alone: such columns are rounding noise and a relative orthogonality
+// test on them never settles.
+// The accumulated rotation W (from the identity) is carried either by the
+// same wave (OFF false) or by a second one (OFF, role 1) that replays the
+// steps as they are published: every step's (cos, sin) per group go to a ring
+// of two sweeps in shared memory (ring [2CHI][CHI/2][2]), then the step count
+// to ctl[0]; the replay reports its progress in ctl[1]; when the sweeps end
+// their total step count goes to ctl[2].  The shared-memory unit serves one
+// wave's accesses in order, so a published count is never seen before the
+// rotations it covers.  The block wave reuses a ring slot only once the
+// replay has passed it (in practice it never waits: the replay has less to
+// do per step).  Every wait is bounded; one that runs out sets ctl[3] and the
+// replay then returns W as NaN, so a lost stream shows in the results
+// instead of hanging the workgroup.  ctl = {published, replayed, total (-1
+// while running), error} must be {0, 0, -1, 0} on entry.
+// Both waves start from the columns ordered by decreasing norm (de Rijk's
+// pivoting, which shortens cyclic Jacobi), each computing the order from the
+// block.  On return the rotated block is back at Tb and W (n x n, same
+// leading dimension) at Wb.  Returns the sweep count (role 0).
+template <typename T, int CHI, bool IL, bool OFF>
+__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *ring, int *ctl) {
+    static_assert(!IL || CHI == 32, "the interleaved layout rotates 16-lane rows");
+    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G, RING = 2 * CHI;
+    constexpr int WAIT_LIMIT = 1 << 22;   // polls of ~64 clocks: ~0.1 s
+    if (!OFF && role != 0) return 0;
+    typedef __attribute__((address_space(3))) T LT;
+    LT *Tl = (LT *)Tb, *Wl = (LT *)Wb;
+    T *rv = ring;
+    int g = IL ? (lane & 15) : lane / G, gl = IL ? (lane >> 4) : lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
-    // Start from the columns ordered by decreasing norm (de Rijk's
-    // pivoting, which shortens cyclic Jacobi): lane l < CHI measures column
-    // l, ranks it among all, and position p takes the column of rank p.
-    // Positions, not column numbers, are written back: the caller ranks the
-    // result by norm, and W's columns follow the block's.
+    // pivoting: lane l < CHI measures column l, ranks it among all, and
+    // position p takes the column of rank p.  Positions, not column
+    // numbers, are written back: the caller ranks the result by norm, and
+    // W's columns follow the block's.
     int src2, src3;
     {
         T nl = (T)-1;
         if (lane < n) {
             T q0 = 0, q1 = 0;
-            const T *cp = Tb + lane * ld;
+            const LT *cp = Tl + lane * ld;
             T q2 = 0, q3 = 0;
             int k = 0;
             for (; k + 3 < K; k += 4) {
@@ -230,66 +311,158 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
         src2 = (int)min((unsigned)__builtin_amdgcn_ds_bpermute((2 * g) << 2, colpos), (unsigned)CHI);
         src3 = (int)min((unsigned)__builtin_amdgcn_ds_bpermute((2 * g + 1) << 2, colpos), (unsigned)CHI);
     }
-    T x[RK], y[RK], wx[RK], wy[RK];
+    const bool blk = role == 0;
+    // x, y: the pair's columns (block, or W in the replay wave); wx, wy: W
+    // in the block wave when it carries W itself
+    T x[RK], y[RK], wx[OFF ? 1 : RK], wy[OFF ? 1 : RK];
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
-        x[i] = (row < K && src2 < n) ? Tb[src2 * ld + row] : (T)0;
-        y[i] = (row < K && src3 < n) ? Tb[src3 * ld + row] : (T)0;
-        wx[i] = (row == src2) ? (T)1 : (T)0;
-        wy[i] = (row == src3) ? (T)1 : (T)0;
+        if (blk) {
+            x[i] = (row < K && src2 < n) ? Tl[src2 * ld + row] : (T)0;
+            y[i] = (row < K && src3 < n) ? Tl[src3 * ld + row] : (T)0;
+        } else {
+            x[i] = (row == src2) ? (T)1 : (T)0;
+            y[i] = (row == src3) ? (T)1 : (T)0;
+        }
+        if constexpr (!OFF) {
+            wx[i] = (row == src2) ? (T)1 : (T)0;
+            wy[i] = (row == src3) ? (T)1 : (T)0;
+        }
     }
     const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
     const bool last = (g == HP - 1);
-    const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
-    const T tol2 = tol * tol;
-    T small = 0;
     int sweeps = 0;
-    for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
-        T a = 0, b = 0;
-#pragma unroll
-        for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
-        if (sw == 0) small = group_sum(a + b, 64) * (T)(1.0 / G) * Eps<T>::v * Eps<T>::v * (T)n;
-        a = group_sum(a, G);
-        b = group_sum(b, G);
-        bool rot = false;
-        for (int t = 0; t < CHI; t += 2) {
-#pragma unroll
-            for (int odd = 0; odd < 2; ++odd) {
-                T c0 = 0, c1 = 0;
-#pragma unroll
-                for (int i = 0; i < RK; i += 2) {
-                    c0 += x[i] * y[i];
-                    if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
-                }
-                const T c = group_sum(c0 + c1, G);
-                T cs, sn;
-                rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
-#pragma unroll
-                for (int i = 0; i < RK; ++i) {
-                    const T u = x[i], v = y[i];
-                    x[i] = cs * u - sn * v;
-                    y[i] = sn * u + cs * v;
-                    const T p = wx[i], q = wy[i];
-                    wx[i] = cs * p - sn * q;
-                    wy[i] = sn * p + cs * q;
-                }
-                if (!odd) {
-                    // even -> odd layout: second column from the next group
-#pragma unroll
-                    for (int i = 0; i < RK; ++i) { y[i] = bperm<T>(up, y[i]); wy[i] = bperm<T>(up, wy[i]); }
-                    b = bperm<T>(up, b);
-                } else {
-                    // odd -> even layout: first column from the previous
-                    // group (the idle last group has exchanged its two)
-#pragma unroll
-                    for (int i = 0; i < RK; ++i) { x[i] = bperm<T>(dn, x[i]); wx[i] = bperm<T>(dn, wx[i]); }
-                    a = bperm<T>(dn, a);
+    if (blk) {
+        const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
+        const T tol2 = tol * tol;
+        T small = 0;
+        int t = 0, slot = 0;
+        for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
+            if constexpr (OFF) {
+                // this sweep reuses the slots of the sweep before the last one
+                if (sw >= 2) {
+                    int polls = 0;
+                    while (lds_poll(ctl + 1) < t - CHI) {
+                        if (++polls > WAIT_LIMIT) { lds_put(ctl + 3, 1); break; }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
                 }
             }
+            T a = 0, b = 0;
+#pragma unroll
+            for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
+            if (sw == 0) small = group_sum(a + b, 64) * (T)(1.0 / G) * Eps<T>::v * Eps<T>::v * (T)n;
+            a = pair_sum<IL>(a, G);
+            b = pair_sum<IL>(b, G);
+            bool rot = false;
+            for (int s = 0; s < CHI; s += 2) {
+#pragma unroll
+                for (int odd = 0; odd < 2; ++odd) {
+                    T c0 = 0, c1 = 0;
+#pragma unroll
+                    for (int i = 0; i < RK; i += 2) {
+                        c0 += x[i] * y[i];
+                        if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
+                    }
+                    const T c = pair_sum<IL>(c0 + c1, G);
+                    T cs, sn;
+                    rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
+                    if constexpr (OFF) {
+                        if (gl == 0) {
+                            lds_put(rv + (slot * HP + g) * 2, cs);
+                            lds_put(rv + (slot * HP + g) * 2 + 1, sn);
+                            lds_order();
+                            if (g == 0) lds_put(ctl, t + 1);
+                        }
+                        ++t;
+                        slot = slot + 1 == RING ? 0 : slot + 1;
+                    }
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) {
+                        const T u = x[i], v = y[i];
+                        x[i] = cs * u - sn * v;
+                        y[i] = sn * u + cs * v;
+                        if constexpr (!OFF) {
+                            const T p = wx[i], q = wy[i];
+                            wx[i] = cs * p - sn * q;
+                            wy[i] = sn * p + cs * q;
+                        }
+                    }
+                    if (!odd) {
+                        // even -> odd layout: second column from the next group
+#pragma unroll
+                        for (int i = 0; i < RK; ++i) {
+                            y[i] = from_next<IL>(y[i], up);
+                            if constexpr (!OFF) wy[i] = from_next<IL>(wy[i], up);
+                        }
+                        b = from_next<IL>(b, up);
+                    } else {
+                        // odd -> even layout: first column from the previous
+                        // group (the idle last group has exchanged its two)
+#pragma unroll
+                        for (int i = 0; i < RK; ++i) {
+                            x[i] = from_prev<IL>(x[i], dn);
+                            if constexpr (!OFF) wx[i] = from_prev<IL>(wx[i], dn);
+                        }
+                        a = from_prev<IL>(a, dn);
+                    }
+                }
+            }
+            ++sweeps;
+            if (__ballot(rot) == 0) break;
         }
-        ++sweeps;
-        if (__ballot(rot) == 0) break;
+        if constexpr (OFF) {
+            lds_order();
+            if (lane == 0) lds_put(ctl + 2, t);
+        }
+    } else if constexpr (OFF) {
+        int t = 0, known = 0, slot = 0;
+        bool bad = false;
+        for (;;) {
+            if (t >= known) {
+                // wait for step t to be published, or for the end
+                int polls = 0;
+                bool end = false;
+                for (;;) {
+                    // the total is read before the count: once set, the
+                    // count already covers it
+                    const int f = lds_poll(ctl + 2);
+                    lds_order();
+                    const int pcount = lds_poll(ctl);
+                    if (pcount > t) { known = pcount; break; }
+                    if (f >= 0 && t >= f) { end = true; break; }
+                    if (lds_poll(ctl + 3) || ++polls > WAIT_LIMIT) { bad = true; end = true; break; }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (end) break;
+            }
+            lds_order();
+            const T cs = lds_get(rv + (slot * HP + g) * 2), sn = lds_get(rv + (slot * HP + g) * 2 + 1);
+#pragma unroll
+            for (int i = 0; i < RK; ++i) {
+                const T u = x[i], v = y[i];
+                x[i] = cs * u - sn * v;
+                y[i] = sn * u + cs * v;
+            }
+            if ((t & 1) == 0) {
+#pragma unroll
+                for (int i = 0; i < RK; ++i) y[i] = from_next<IL>(y[i], up);
+            } else {
+#pragma unroll
+                for (int i = 0; i < RK; ++i) x[i] = from_prev<IL>(x[i], dn);
+            }
+            ++t;
+            slot = slot + 1 == RING ? 0 : slot + 1;
+            lds_order();
+            if (lane == 0) lds_put(ctl + 1, t);
+        }
+        if (bad || lds_poll(ctl + 3)) {
+            lds_put(ctl + 3, 1);
+#pragma unroll
+            for (int i = 0; i < RK; ++i) { x[i] = __builtin_nan(""); y[i] = __builtin_nan(""); }
+        }
+        sweeps = t / CHI;
     }
     // after an odd number of sweeps the positions are reversed
     const bool rev = sweeps & 1;
@@ -297,16 +470,23 @@ __device__ int jacobi_one(T *Tb, T *Wb, int ld, int K, int n, int lane) {
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
-        if (row < K) {
-            if (cx < n) Tb[cx * ld + row] = x[i];
-            if (cy < n) Tb[cy * ld + row] = y[i];
-        }
-        if (row < n) {
-            if (cx < n) Wb[cx * ld + row] = wx[i];
-            if (cy < n) Wb[cy * ld + row] = wy[i];
+        if (blk) {
+            if (row < K) {
+                if (cx < n) Tl[cx * ld + row] = x[i];
+                if (cy < n) Tl[cy * ld + row] = y[i];
+            }
+            if constexpr (!OFF) {
+                if (row < n) {
+                    if (cx < n) Wl[cx * ld + row] = wx[i];
+                    if (cy < n) Wl[cy * ld + row] = wy[i];
+                }
+            }
+        } else if (row < n) {
+            if (cx < n) Wl[cx * ld + row] = x[i];
+            if (cy < n) Wl[cy * ld + row] = y[i];
         }
     }
-    return sweeps;
+    return blk ? sweeps : 0;
 }
 
 // One-sided (Hestenes) Jacobi on one block with the block in one wave's
@@ -446,17 +626,25 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
 // The register Jacobi for the smallest compiled width that holds chi; MAXB
 // is the widest one compiled into this kernel (wider paths only cost
 // registers, so a kernel carries the ones its launch needs).  Called by all
-// four waves: for chi <= 32 waves 0 and 1 each run one block alone; for
-// chi = 64 waves 2 and 3 carry the blocks' rotations (role 1).
+// four waves: waves 0 and 1 hold the blocks (role 0), waves 2 and 3 their
+// rotations W (role 1); for chi <= 32 through the rotation ring and control
+// words of the block (ring, ctl), for chi = 64 through prm and flags.
+// Whether the chi <= 32 Jacobi of arithmetic type T streams its rotations to
+// a second wave (and the build holds the rotation rings).
+template <typename T> constexpr bool RINGS_OF = sizeof(T) == 8;
+
 template <typename T, int MAXB>
 __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
-                            int *flags) {
+                            int *flags, T *ring, int *ctl) {
     if constexpr (MAXB >= 64) {
         if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
     }
-    if (role != 0) return 0;
-    if (chi <= 16) return jacobi_one<T, 16>(Tb, Wb, ld, K, n, lane);
-    return jacobi_one<T, 32>(Tb, Wb, ld, K, n, lane);
+    // chi <= 32: interleaved groups; W in a second wave for float64 only (a
+    // float step is bound by its dependency chain, which the W rotations
+    // fill; a float64 step by its issue, which they lengthen)
+    constexpr bool OFF = RINGS_OF<T>;
+    if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
+    return jacobi_reg<T, 32, true, OFF>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
 }
 
 // One site of the QR sweep for both parity blocks, held in registers.
@@ -678,7 +866,8 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     // for chi <= 32 the SVD phase also holds the next site's Q slot, staged
     // by waves 2 and 3 while waves 0 and 1 run the Jacobi
     const bool qstage = CB <= 32;
-    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 : 0);  // SVD phase
+    // and, for chi <= 32 in float64, the two blocks' Jacobi rotation rings
+    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 + (RINGS_OF<T> ? 4 * CB * CB : 0) : 0);
     T *reg = reinterpret_cast<T *>(smem);
     T *C = reg;                       // [CB][CB]
     T *R = reg + CB * CB;             // [2][CB][CB]
@@ -687,6 +876,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
     T *X = reg + 4 * bst;             // [2][chi][chi]
     T *Qst = X + 2 * cc2;             // [2][2chi][chi] staged Q slot (chi <= 32)
+    T *jring = Qst + 4 * cc2;         // [2][2CB][CB/2][2] rotation rings (chi <= 32, float64)
     T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
     T *tau = tail;                    // [2][CB]
     T *nrm = tau + 2 * CB;            // [2][chi+2]
@@ -699,7 +889,8 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     int *rankv = colof + 2 * chi + 4;                 // [2chi+4]
     int *iflag = rankv + 2 * chi + 4;                 // [4]
     int *jflag = iflag + 4;                           // [2] Jacobi: block still rotating
-    unsigned char *dsec = reinterpret_cast<unsigned char *>(jflag + 2);  // [L+1][2] bond sectors
+    int *jctl = jflag + 2;                            // [2][4] Jacobi rotation streams
+    unsigned char *dsec = reinterpret_cast<unsigned char *>(jctl + 8);   // [L+1][2] bond sectors
     unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
 
     int total_sweeps = 0;
@@ -891,19 +1082,21 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 };
                 if (qstage) tform(Qst); else tform(q);
             }
+            if (tid < 8) jctl[tid] = (tid & 3) == 2 ? -1 : 0;   // {published, replayed, total, error}
             __syncthreads();
             {
                 const long long t0 = wall_clock64();
                 // waves 0, 1: blocks 0, 1; waves 2, 3: their rotations
                 const int wv = tid >> 6, pb = wv & 1;
-                const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
-                                                     tid & 63, wv >> 1, pb, jprm, jflag);
-                if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 if (qstage && wv >= 2) {
-                    // meanwhile: the next site's Q slot into shared memory
+                    // first: the next site's Q slot into shared memory
                     const T *src = qscr + (size_t)(c - 1) * 4 * cc2;
                     for (int e = tid - 128; e < 4 * cc2; e += 128) Qst[e] = src[e];
                 }
+                const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
+                                                     tid & 63, wv >> 1, pb, jprm, jflag,
+                                                     jring + pb * 2 * CB * CB, jctl + 4 * pb);
+                if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                 cyc_jac += wall_clock64() - t0;
