@@ -417,45 +417,63 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
             if (lane == 0) lds_put(ctl + 2, t);
         }
     } else if constexpr (OFF) {
-        int t = 0, known = 0, slot = 0;
+        // replay in batches of RB published steps: the rotations of a batch
+        // are read together, and a wait costs one poll per batch, not per
+        // step
+        constexpr int RB = 4;
+        int t = 0, slot = 0;
         bool bad = false;
         for (;;) {
-            if (t >= known) {
-                // wait for step t to be published, or for the end
-                int polls = 0;
-                bool end = false;
-                for (;;) {
-                    // the total is read before the count: once set, the
-                    // count already covers it
-                    const int f = lds_poll(ctl + 2);
-                    lds_order();
-                    const int pcount = lds_poll(ctl);
-                    if (pcount > t) { known = pcount; break; }
-                    if (f >= 0 && t >= f) { end = true; break; }
-                    if (lds_poll(ctl + 3) || ++polls > WAIT_LIMIT) { bad = true; end = true; break; }
-                    __builtin_amdgcn_s_sleep(1);
+            // wait for RB more steps, or for the end
+            int polls = 0, avail = 0;
+            for (;;) {
+                // the total is read before the count: once set, the count
+                // already covers it
+                const int f = lds_poll(ctl + 2);
+                lds_order();
+                const int pcount = lds_poll(ctl);
+                if (pcount >= t + RB || (f >= 0 && pcount > t)) { avail = pcount - t; break; }
+                if (f >= 0 && t >= f) break;
+                if (lds_poll(ctl + 3) || ++polls > WAIT_LIMIT) { bad = true; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (avail == 0) break;
+            lds_order();
+            while (avail > 0) {
+                const int nb = avail < RB ? avail : RB;
+                T cs[RB], sn[RB];
+#pragma unroll
+                for (int j = 0; j < RB; ++j) {
+                    int sj = slot + j;
+                    sj = sj >= RING ? sj - RING : sj;
+                    cs[j] = j < nb ? lds_get(rv + (sj * HP + g) * 2) : (T)1;
+                    sn[j] = j < nb ? lds_get(rv + (sj * HP + g) * 2 + 1) : (T)0;
                 }
-                if (end) break;
-            }
-            lds_order();
-            const T cs = lds_get(rv + (slot * HP + g) * 2), sn = lds_get(rv + (slot * HP + g) * 2 + 1);
 #pragma unroll
-            for (int i = 0; i < RK; ++i) {
-                const T u = x[i], v = y[i];
-                x[i] = cs * u - sn * v;
-                y[i] = sn * u + cs * v;
-            }
-            if ((t & 1) == 0) {
+                for (int j = 0; j < RB; ++j) {
+                    if (j < nb) {
 #pragma unroll
-                for (int i = 0; i < RK; ++i) y[i] = from_next<IL>(y[i], up);
-            } else {
+                        for (int i = 0; i < RK; ++i) {
+                            const T u = x[i], v = y[i];
+                            x[i] = cs[j] * u - sn[j] * v;
+                            y[i] = sn[j] * u + cs[j] * v;
+                        }
+                        if (((t + j) & 1) == 0) {
 #pragma unroll
-                for (int i = 0; i < RK; ++i) x[i] = from_prev<IL>(x[i], dn);
+                            for (int i = 0; i < RK; ++i) y[i] = from_next<IL>(y[i], up);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < RK; ++i) x[i] = from_prev<IL>(x[i], dn);
+                        }
+                    }
+                }
+                t += nb;
+                slot += nb;
+                slot = slot >= RING ? slot - RING : slot;
+                avail -= nb;
+                lds_order();
+                if (lane == 0) lds_put(ctl + 1, t);
             }
-            ++t;
-            slot = slot + 1 == RING ? 0 : slot + 1;
-            lds_order();
-            if (lane == 0) lds_put(ctl + 1, t);
         }
         if (bad || lds_poll(ctl + 3)) {
             lds_put(ctl + 3, 1);
