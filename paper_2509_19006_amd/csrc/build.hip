@@ -52,7 +52,7 @@ size_t build_lds_bytes(int chi, int L, size_t tsize) {
     const size_t cb = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);
     const size_t regA = 7 * cb * cb;
     const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi +
-                        (cb <= 32 ? (size_t)4 * chi * chi + (tsize == 8 ? 4 * cb * cb : 0) : 0);   // + Q slot, rings
+                        (cb <= 32 ? (size_t)4 * chi * chi + 4 * cb * cb : 0);   // + Q slot, rings
     size_t elems = (regA > regS ? regA : regS);
     elems += 2 * cb + 2 * (chi + 2) + 4 * cb;                 // tau, nrm, Jacobi rotations
     size_t bytes = elems * tsize;

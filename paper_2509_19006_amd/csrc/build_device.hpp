@@ -369,12 +369,14 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
                     T cs, sn;
                     rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
                     if constexpr (OFF) {
-                        if (gl == 0) {
-                            lds_put(rv + (slot * HP + g) * 2, cs);
-                            lds_put(rv + (slot * HP + g) * 2 + 1, sn);
-                            lds_order();
-                            if (g == 0) lds_put(ctl, t + 1);
-                        }
+                        // every lane writes: a group's lanes store the same
+                        // values to the same words (a lane mask here would
+                        // split the step into basic blocks the scheduler
+                        // cannot overlap)
+                        lds_put(rv + (slot * HP + g) * 2, cs);
+                        lds_put(rv + (slot * HP + g) * 2 + 1, sn);
+                        lds_order();
+                        lds_put(ctl, t + 1);
                         ++t;
                         slot = slot + 1 == RING ? 0 : slot + 1;
                     }
@@ -645,24 +647,29 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
 // is the widest one compiled into this kernel (wider paths only cost
 // registers, so a kernel carries the ones its launch needs).  Called by all
 // four waves: waves 0 and 1 hold the blocks (role 0), waves 2 and 3 their
-// rotations W (role 1); for chi <= 32 through the rotation ring and control
-// words of the block (ring, ctl), for chi = 64 through prm and flags.
-// Whether the chi <= 32 Jacobi of arithmetic type T streams its rotations to
-// a second wave (and the build holds the rotation rings).
-template <typename T> constexpr bool RINGS_OF = sizeof(T) == 8;
-
+// rotations W (role 1), for 16 < chi <= 32 through the rotation ring and
+// control words of the block (ring, ctl), for chi = 64 through prm and
+// flags; for chi <= 16 the block's wave carries W itself.
 template <typename T, int MAXB>
 __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
                             int *flags, T *ring, int *ctl) {
     if constexpr (MAXB >= 64) {
         if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
     }
-    // chi <= 32: interleaved groups; W in a second wave for float64 only (a
-    // float step is bound by its dependency chain, which the W rotations
-    // fill; a float64 step by its issue, which they lengthen)
-    constexpr bool OFF = RINGS_OF<T>;
+    // chi <= 16: contiguous groups, W in the block's wave; chi <= 32:
+    // interleaved groups, W in a second wave
     if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
-    return jacobi_reg<T, 32, true, OFF>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
+    return jacobi_reg<T, 32, true, true>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
+}
+
+// Sum over a lane's rows of a[r] * b[r] in four independent partial sums
+// (a single running sum is one dependent chain as long as the rows).
+template <typename T, int RR>
+__device__ __forceinline__ T rows_dot(const T (&a)[RR], const T (&b)[RR]) {
+    T s[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < RR; ++r) s[r & 3] += a[r] * b[r];
+    return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // One site of the QR sweep for both parity blocks, held in registers.
@@ -756,13 +763,14 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     for (int j = 0; j < mc; ++j) {
         T *vj = V + (p * CHI + j) * 2 * CHI;
         if (grp == j) {
-            T s = 0, x0 = 0;
+            T x0 = 0, tail[RR];
 #pragma unroll
             for (int r = 0; r < RR; ++r) {
                 const int row = row0 + r;
-                if (row > j) s += m[r] * m[r];
+                tail[r] = row > j ? m[r] : (T)0;
                 if (row == j) x0 = m[r];
             }
+            T s = rows_dot<T, RR>(tail, tail);
             s = group_sum(s, G);
             x0 = group_sum(x0, G);
             T tj = 0, sc = 0, be = x0;
@@ -784,9 +792,10 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
         if (grp > j) {
             const T tj = tauv[p * CHI + j];
             if (tj != (T)0) {
-                T w = 0;
+                T vr[RR];
 #pragma unroll
-                for (int r = 0; r < RR; ++r) w += vj[row0 + r] * m[r];
+                for (int r = 0; r < RR; ++r) vr[r] = vj[row0 + r];
+                T w = rows_dot<T, RR>(vr, m);
                 w = group_sum(w, G) * tj;
 #pragma unroll
                 for (int r = 0; r < RR; ++r) m[r] -= vj[row0 + r] * w;
@@ -801,9 +810,10 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
         const T tj = tauv[p * CHI + j];
         if (tj == (T)0 || grp < j) continue;
         const T *vj = V + (p * CHI + j) * 2 * CHI;
-        T w = 0;
+        T vr[RR];
 #pragma unroll
-        for (int r = 0; r < RR; ++r) w += vj[row0 + r] * qv[r];
+        for (int r = 0; r < RR; ++r) vr[r] = vj[row0 + r];
+        T w = rows_dot<T, RR>(vr, qv);
         w = group_sum(w, G) * tj;
 #pragma unroll
         for (int r = 0; r < RR; ++r) qv[r] -= vj[row0 + r] * w;
@@ -884,8 +894,8 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     // for chi <= 32 the SVD phase also holds the next site's Q slot, staged
     // by waves 2 and 3 while waves 0 and 1 run the Jacobi
     const bool qstage = CB <= 32;
-    // and, for chi <= 32 in float64, the two blocks' Jacobi rotation rings
-    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 + (RINGS_OF<T> ? 4 * CB * CB : 0) : 0);
+    // and, for chi <= 32, the two blocks' Jacobi rotation rings
+    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 + 4 * CB * CB : 0);
     T *reg = reinterpret_cast<T *>(smem);
     T *C = reg;                       // [CB][CB]
     T *R = reg + CB * CB;             // [2][CB][CB]
@@ -894,7 +904,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
     T *X = reg + 4 * bst;             // [2][chi][chi]
     T *Qst = X + 2 * cc2;             // [2][2chi][chi] staged Q slot (chi <= 32)
-    T *jring = Qst + 4 * cc2;         // [2][2CB][CB/2][2] rotation rings (chi <= 32, float64)
+    T *jring = Qst + 4 * cc2;         // [2][2CB][CB/2][2] rotation rings (chi <= 32)
     T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
     T *tau = tail;                    // [2][CB]
     T *nrm = tau + 2 * CB;            // [2][chi+2]
