@@ -59,7 +59,8 @@ size_t build_lds_bytes(int chi, int L, size_t tsize) {
     bytes = (bytes + 7) & ~(size_t)7;
     bytes += (NT / 64 + 128 + 8) * sizeof(double);           // red, uvec, scal
     bytes += (2 * (2 * chi + 4) + 4 + 2 + 8) * sizeof(int);  // colof, rankv, iflag, jflag, jctl
-    bytes += (size_t)4 * (L + 1);                            // dsec, mq
+    bytes += (size_t)4 * (L + 1) + 4;                        // dsec, mq (+ alignment)
+    bytes += (size_t)4 * 2 * L;                              // the row's couplings
     return (bytes + 15) & ~(size_t)15;
 }
 

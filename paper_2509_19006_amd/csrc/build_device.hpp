@@ -672,16 +672,29 @@ __device__ __forceinline__ T rows_dot(const T (&a)[RR], const T (&b)[RR]) {
     return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
+// Column swizzle of the carried factor R: element (qk, a) of R [2CHI rows]
+// is stored at qk*CHI + (a ^ rkey(qk)).  The lanes of a group read rows
+// RR apart, which without it fall in the same LDS banks (a row is CHI words
+// long); the key moves their 16-byte column chunks to different banks and
+// keeps the chunks aligned.  Returns qk*CHI + rkey(qk): XOR with a column
+// index (< CHI) gives the element.
+template <int CHI, int RR> __device__ __forceinline__ int rkey_base(int qk) {
+    return qk * CHI + (((qk / RR) & 3) << 2);
+}
+
 // One site of the QR sweep for both parity blocks, held in registers.
 // Block p belongs to waves 2p and 2p+1 (128 lanes); lane group grp (G =
 // 128/CHI lanes) owns column grp of M^p and each of its lanes RR = 2CHI/G
 // consecutive rows.  Shared memory (CHI-strided): C [CHI][CHI] (row a of the
 // old left bond, column b of the old right bond), R [2][CHI][CHI] (the
-// factor carried from the previous site, zero outside its trapezoid),
-// V [2][CHI][2CHI] (Householder vectors), tauv [2][CHI].
+// factor carried from the previous site, already scaled into Rh, zero
+// outside its trapezoid; element (qk, a) at qk*CHI + (a ^ rkey(qk)), see
+// rkey), V [2][CHI][2CHI] (Householder vectors), tauv [2][CHI].
 //   M^p rows: sigma = 0 -> Rh^p C (m_p rows), sigma = 1 -> Rh^(1-p) C, where
 //   Rh^q scales column a of R^q by lam_h[(a's sector) ^ q]; at c = 0 the
-//   single row is C's first row.
+//   single row is C's first row.  The scaling belongs to the next site's
+//   horizontal bond and is applied where R is written (lnh0, lnh1: its
+//   eigenvalues; pn0: the even sector size of the bond R leaves to).
 //   Householder QR (LAPACK's reflector convention): per column j the owner
 //   group publishes v_j and tau_j, every later column applies H_j.  The
 //   explicit Q (K x mc) goes to qdst ([2][2chi][chi], row-major, stride chi);
@@ -690,8 +703,8 @@ __device__ __forceinline__ T rows_dot(const T (&a)[RR], const T (&b)[RR]) {
 // (the centre of the sweep) and nothing is factored.  Returns ln of the
 // joint norm (0 at the last site) and mc.
 template <typename T, int CHI>
-__device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, T lh0, T lh1,
-                          const T *C, T *R, T *V, T *tauv, T *qdst, int chi, double *red, int &mc_out,
+__device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, int pn0, T lnh0,
+                          T lnh1, const T *C, T *R, T *V, T *tauv, T *qdst, int chi, double *red, int &mc_out,
                           long long &cyc_hh) {
     constexpr int G = 128 / CHI, RR = 2 * CHI / G;
     const int tid = threadIdx.x, p = tid >> 7, lt = tid & 127;
@@ -708,47 +721,35 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
 #pragma unroll
         for (int r = 0; r < RR; ++r) m[r] = (row0 + r == 0) ? x : (T)0;
     } else {
-        // M = sum_a R_q[k][a] C[a][grp] lam_h[...]: chunks of 4 columns of C
-        // against the rows' R entries, sectors accumulated apart
+        // M = sum_a Rh_q[k][a] C[a][grp]: chunks of 4 columns of C against
+        // the rows' Rh entries
         int roff[RR];
-        T accE[RR], accO[RR];
+        T acc[RR];
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
             const int row = row0 + r;
             const int q = (row < mp) ? p : 1 - p;
             const int k = (row < K) ? ((row < mp) ? row : row - mp) : 0;
-            roff[r] = (q * CHI + k) * CHI;
-            accE[r] = 0;
-            accO[r] = 0;
+            roff[r] = rkey_base<CHI, RR>(q * CHI + k);
+            acc[r] = 0;
         }
 #pragma unroll 1
         for (int a0 = 0; a0 < CHI; a0 += 4) {
-            T ce[4], co[4];
+            T cv[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int a = a0 + i;
-                const T x = (a < Dp && grp < D) ? C[a * CHI + grp] : (T)0;
-                ce[i] = (a < pa0) ? x : (T)0;
-                co[i] = (a < pa0) ? (T)0 : x;
+                cv[i] = (a < Dp && grp < D) ? C[a * CHI + grp] : (T)0;
             }
 #pragma unroll
             for (int r = 0; r < RR; ++r) {
-                const T *Rq = R + roff[r] + a0;
+                const T *Rq = R + (roff[r] ^ a0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const T rv = Rq[i];
-                    accE[r] += rv * ce[i];
-                    accO[r] += rv * co[i];
-                }
+                for (int i = 0; i < 4; ++i) acc[r] += Rq[i] * cv[i];
             }
         }
 #pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            const int row = row0 + r;
-            const bool q1 = (row < mp) ? (p == 1) : (p == 0);
-            const T v = q1 ? lh1 * accE[r] + lh0 * accO[r] : lh0 * accE[r] + lh1 * accO[r];
-            m[r] = (row < K) ? v : (T)0;
-        }
+        for (int r = 0; r < RR; ++r) m[r] = (row0 + r < K) ? acc[r] : (T)0;
     }
     if (last) {
         if (p == 0 && grp == 0) {
@@ -825,6 +826,8 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     }
     cyc_hh += wall_clock64() - th0;
     // R^p (mc x D, upper trapezoidal), normalised jointly over both blocks
+    // and scaled into Rh^p for the next site: column a by lam_h[(a's
+    // sector) ^ p] of the next horizontal bond
     double part = 0.0;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
@@ -836,22 +839,24 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
         const int row = row0 + r;
-        if (row < CHI) R[(p * CHI + row) * CHI + grp] = (row < mc && row <= grp && grp < D) ? m[r] * inv : (T)0;
+        const T lam = ((grp >= pn0) != (p == 1)) ? lnh1 : lnh0;
+        if (row < CHI)
+            R[rkey_base<CHI, RR>(p * CHI + row) ^ grp] = (row < mc && row <= grp && grp < D) ? (m[r] * inv) * lam : (T)0;
     }
     mc_out = mc;
     return log(nu);
 }
 
 template <typename T, int MAXB>
-__device__ double qr_site_any(int chi, int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, T lh0,
-                              T lh1, const T *C, T *R, T *V, T *tauv, T *qdst, double *red, int &mc,
+__device__ double qr_site_any(int chi, int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, int pn0,
+                              T lnh0, T lnh1, const T *C, T *R, T *V, T *tauv, T *qdst, double *red, int &mc,
                               long long &cyc_hh) {
-    if (chi <= 16) return qr_site<T, 16>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+    if (chi <= 16) return qr_site<T, 16>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
     if constexpr (MAXB <= 32) {
-        return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
     } else {
-        if (chi <= 32) return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
-        return qr_site<T, 64>(c, last, K, D, Dp, pa0, m0, m1, lh0, lh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        if (chi <= 32) return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        return qr_site<T, 64>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
     }
 }
 
@@ -920,6 +925,8 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     int *jctl = jflag + 2;                            // [2][4] Jacobi rotation streams
     unsigned char *dsec = reinterpret_cast<unsigned char *>(jctl + 8);   // [L+1][2] bond sectors
     unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
+    // the current row's couplings (vertical, then horizontal)
+    float *jrow = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(mq + 2 * (L + 1)) + 3) & ~(uintptr_t)3);
 
     int total_sweeps = 0;
     long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0, cyc_hh = 0;   // wall-clock ticks per phase
@@ -975,37 +982,89 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 
         double part = 0.0;
         for (int c = tid; c < L; c += NT) {
-            part += beta * fabs((double)jv[(size_t)r * L + c]);
-            if (c < L - 1) part += beta * fabs((double)jh[(size_t)r * (L - 1) + c]);
+            const float v = jv[(size_t)r * L + c];
+            jrow[c] = v;
+            part += beta * fabs((double)v);
+            if (c < L - 1) {
+                const float h = jh[(size_t)r * (L - 1) + c];
+                jrow[L + c] = h;
+                part += beta * fabs((double)h);
+            }
         }
-        double ls = block_sum(part, red) - (double)(L - 1) * LN2;
+        double ls = block_sum(part, red) - (double)(L - 1) * LN2;   // (its barriers publish jrow)
 
         // ================= QR sweep, left to right =========================
         const long long tq0 = wall_clock64();
         if (tid == 0) { mq[0] = 1; mq[1] = 0; }
         __syncthreads();
+        // The previous row's site c + 1 is read into registers while site c
+        // is factored (chi <= 32 kernels; the chi = 64 kernel reads each
+        // site in place, all loads before the stores).
+        constexpr int CPT = MAXB <= 32 ? MAXB * MAXB / NT : 1;
+        T pre[CPT];
+        auto fetch_site = [&](int cs) {
+            const int pa0 = dsec[2 * cs], Dp = pa0 + dsec[2 * cs + 1];
+            const int pb0 = dsec[2 * (cs + 1)], D = pb0 + dsec[2 * (cs + 1) + 1];
+            const T *os = orow + (size_t)cs * site_sz;
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) {
+                const int e = tid + i * NT;
+                const int a = e / D, b = e % D;
+                const int n = (a >= pa0) ^ (b >= pb0);
+                pre[i] = e < Dp * D ? os[n * cc2 + a * chi + b] : (T)0;
+            }
+        };
+        if constexpr (MAXB <= 32) fetch_site(0);
         for (int c = 0; c < L; ++c) {
             const int pa0 = dsec[2 * c], Dp = pa0 + dsec[2 * c + 1];             // old left bond
             const int pb0 = dsec[2 * (c + 1)], D = pb0 + dsec[2 * (c + 1) + 1];  // old right bond
             const int m0 = mq[2 * c], m1 = mq[2 * c + 1];
             const int K = m0 + m1;
             double lv0, lv1;
-            lam_of(beta, jv[(size_t)r * L + c], lv0, lv1);
+            lam_of(beta, jrow[c], lv0, lv1);
             // (a) C[a][b] = lam_v[pa^pb] * A_old[pa^pb][a][b]
-            const T *os = orow + (size_t)c * site_sz;
-            for (int e = tid; e < Dp * D; e += NT) {
-                const int a = e / D, b = e % D;
-                const int n = (a >= pa0) ^ (b >= pb0);
-                C[a * CB + b] = (T)(n ? lv1 : lv0) * os[n * cc2 + a * chi + b];
+            if constexpr (MAXB <= 32) {
+#pragma unroll
+                for (int i = 0; i < CPT; ++i) {
+                    const int e = tid + i * NT;
+                    if (e < Dp * D) {
+                        const int a = e / D, b = e % D;
+                        const int n = (a >= pa0) ^ (b >= pb0);
+                        C[a * CB + b] = (T)(n ? lv1 : lv0) * pre[i];
+                    }
+                }
+                if (c + 1 < L) fetch_site(c + 1);
+            } else {
+                const T *os = orow + (size_t)c * site_sz;
+                constexpr int CPW = MAXB * MAXB / NT;
+                T v[CPW];
+#pragma unroll
+                for (int i = 0; i < CPW; ++i) {
+                    const int e = tid + i * NT;
+                    const int a = e / D, b = e % D;
+                    const int n = (a >= pa0) ^ (b >= pb0);
+                    v[i] = e < Dp * D ? os[n * cc2 + a * chi + b] : (T)0;
+                }
+#pragma unroll
+                for (int i = 0; i < CPW; ++i) {
+                    const int e = tid + i * NT;
+                    if (e < Dp * D) {
+                        const int a = e / D, b = e % D;
+                        const int n = (a >= pa0) ^ (b >= pb0);
+                        C[a * CB + b] = (T)(n ? lv1 : lv0) * v[i];
+                    }
+                }
             }
-            double lh0 = 0.0, lh1 = 0.0;
-            if (c > 0) lam_of(beta, jh[(size_t)r * (L - 1) + (c - 1)], lh0, lh1);
+            // the next horizontal bond's eigenvalues: the carried R is scaled
+            // by them where it is written
+            double ln0 = 1.0, ln1 = 1.0;
+            if (c + 1 < L) lam_of(beta, jrow[L + c], ln0, ln1);
             __syncthreads();
             // (b)-(f) in registers: M^p, Householder QR, explicit Q to scratch
-            // slot c, normalised R carried right
+            // slot c, normalised and scaled R carried right
             int mc = 1;
-            ls += qr_site_any<T, MAXB>(chi, c, c == L - 1, K, D, Dp, pa0, m0, m1, (T)lh0, (T)lh1, C, R, Vh, tau,
-                                 qscr + (size_t)c * 4 * cc2, red, mc, cyc_hh);
+            ls += qr_site_any<T, MAXB>(chi, c, c == L - 1, K, D, Dp, pa0, m0, m1, pb0, (T)ln0, (T)ln1, C, R, Vh,
+                                       tau, qscr + (size_t)c * 4 * cc2, red, mc, cyc_hh);
             if (c == L - 1) {
                 if (tid == 0) { mq[2 * L] = 1; mq[2 * L + 1] = 0; }
                 __syncthreads();
