@@ -50,7 +50,8 @@ TNMC_LB(float, __half)
 // Shared-memory bytes the build kernel needs for bond dimension chi and side L.
 size_t build_lds_bytes(int chi, int L, size_t tsize) {
     const size_t cb = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);
-    const size_t regA = 7 * cb * cb;
+    const size_t vl = 2 * cb + (128 / cb - 1) * (cb >= 32 ? 4 : 0);   // padded Householder vector
+    const size_t regA = 3 * cb * cb + 2 * cb * vl;
     const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi +
                         (cb <= 32 ? (size_t)4 * chi * chi + 4 * cb * cb : 0);   // + Q slot, rings
     size_t elems = (regA > regS ? regA : regS);

@@ -682,6 +682,13 @@ template <int CHI, int RR> __device__ __forceinline__ int rkey_base(int qk) {
     return qk * CHI + (((qk / RR) & 3) << 2);
 }
 
+// Householder vectors in shared memory: a lane group's lanes hold RR
+// consecutive rows each, so for CHI >= 32 their segments would start on the
+// same LDS banks; each segment is padded by 4 words.  Row stride of V:
+template <int CHI> constexpr int vrow_len() {
+    return 2 * CHI + (128 / CHI - 1) * (CHI >= 32 ? 4 : 0);
+}
+
 // One site of the QR sweep for both parity blocks, held in registers.
 // Block p belongs to waves 2p and 2p+1 (128 lanes); lane group grp (G =
 // 128/CHI lanes) owns column grp of M^p and each of its lanes RR = 2CHI/G
@@ -698,6 +705,8 @@ template <int CHI, int RR> __device__ __forceinline__ int rkey_base(int qk) {
 //   Householder QR (LAPACK's reflector convention): per column j the owner
 //   group publishes v_j and tau_j, every later column applies H_j.  The
 //   explicit Q (K x mc) goes to qdst ([2][2chi][chi], row-major, stride chi);
+//   V holds vector j of block p at (p CHI + j) vrow_len, row r of a lane's
+//   segment at its padded offset.
 //   R (mc x D, normalised jointly over both blocks) replaces the R array.
 // At the last site (D = 1) only block 0's single column is written to qdst
 // (the centre of the sweep) and nothing is factored.  Returns ln of the
@@ -714,6 +723,8 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     // would stay live across the whole build)
     asm volatile("" : "+v"(grp), "+v"(row0));
     const int gl = row0 / RR;
+    const int vrow0 = row0 + gl * (CHI >= 32 ? 4 : 0);   // padded start of the lane's rows in V
+    constexpr int VL = vrow_len<CHI>();
     const int mp = p ? m1 : m0;
     T m[RR];
     if (c == 0) {
@@ -762,7 +773,7 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     const long long th0 = wall_clock64();
     const int mc = K < D ? K : D;
     for (int j = 0; j < mc; ++j) {
-        T *vj = V + (p * CHI + j) * 2 * CHI;
+        T *vj = V + (p * CHI + j) * VL;
         if (grp == j) {
             T x0 = 0, tail[RR];
 #pragma unroll
@@ -784,7 +795,7 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
 #pragma unroll
             for (int r = 0; r < RR; ++r) {
                 const int row = row0 + r;
-                vj[row] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
+                vj[vrow0 + r] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
                 m[r] = row < j ? m[r] : (row == j ? be : (T)0);
             }
             if (gl == 0) tauv[p * CHI + j] = tj;
@@ -795,11 +806,11 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
             if (tj != (T)0) {
                 T vr[RR];
 #pragma unroll
-                for (int r = 0; r < RR; ++r) vr[r] = vj[row0 + r];
+                for (int r = 0; r < RR; ++r) vr[r] = vj[vrow0 + r];
                 T w = rows_dot<T, RR>(vr, m);
                 w = group_sum(w, G) * tj;
 #pragma unroll
-                for (int r = 0; r < RR; ++r) m[r] -= vj[row0 + r] * w;
+                for (int r = 0; r < RR; ++r) m[r] -= vr[r] * w;
             }
         }
     }
@@ -810,14 +821,14 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     for (int j = mc - 1; j >= 0; --j) {
         const T tj = tauv[p * CHI + j];
         if (tj == (T)0 || grp < j) continue;
-        const T *vj = V + (p * CHI + j) * 2 * CHI;
+        const T *vj = V + (p * CHI + j) * VL;
         T vr[RR];
 #pragma unroll
-        for (int r = 0; r < RR; ++r) vr[r] = vj[row0 + r];
+        for (int r = 0; r < RR; ++r) vr[r] = vj[vrow0 + r];
         T w = rows_dot<T, RR>(vr, qv);
         w = group_sum(w, G) * tj;
 #pragma unroll
-        for (int r = 0; r < RR; ++r) qv[r] -= vj[row0 + r] * w;
+        for (int r = 0; r < RR; ++r) qv[r] -= vr[r] * w;
     }
     if (grp < mc) {
         T *qd = qdst + (size_t)p * 2 * chi * chi + grp;
@@ -860,6 +871,50 @@ __device__ double qr_site_any(int chi, int c, int last, int K, int D, int Dp, in
     }
 }
 
+// The SVD centre T^p = [Q^p_0 X^p, Q^(1-p)_1 X^(1-p)] in float for chi <= 32
+// on the matrix cores: wave 2p + s forms part s of block p as one 32 x 32 x 32
+// product (v_mfma_f32_32x32x2f32, 16 steps of 2), rows, columns and the
+// inner length masked to the blocks' sizes.  Operand layouts: lane l holds
+// A[l % 32][k0 + l / 32] and B[k0 + l / 32][l % 32]; result register r of lane
+// l is D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  Qs: the Q slot [2][2chi][chi]
+// (rows of block q: its sigma = 0 part, K_q rows, then its sigma = 1 part), X
+// [2][chi][chi], Tm [2][bst] column-major with leading dimension ldt; K0, K1:
+// the blocks' rows; r0, r1: the right bond's sectors (kr = r0 + r1 columns
+// with data, n >= kr written); mn0, mn1: inner lengths.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ void tform_mfma(const float *Qs, const float *X, float *Tm, int chi, int ldt, int bst,
+                                           int K0, int K1, int r0, int r1, int mn0, int mn1, int n) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int p = w >> 1, s = w & 1;
+    const int Kp = p ? K1 : K0;
+    const int qb = s ? 1 - p : p;                   // block of Q and X
+    const int rowoff = s ? (qb ? K1 : K0) : 0;      // sigma = 1 rows follow the K_qb sigma = 0 rows
+    const int mn = qb ? mn1 : mn0;
+    const int dp = p ? r1 : r0;
+    const int c0 = s ? dp : 0;                      // first column of the part
+    const int wdata = s ? (r0 + r1) - dp : dp;      // columns with data
+    const int wout = s ? n - dp : dp;               // columns written (part 1 includes the padding)
+    const float *Qb = Qs + qb * 2 * chi * chi + rowoff * chi;
+    const float *Xb = X + qb * chi * chi;
+    const int i = l & 31, kh = l >> 5;
+    floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 2) {
+        const int j = k0 + kh;
+        const float a = (i < Kp && j < mn) ? Qb[i * chi + j] : 0.f;
+        const float b = (j < mn && i < wdata) ? Xb[j * chi + i] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    if (i < wout) {
+        float *col = Tm + p * bst + (c0 + i) * ldt;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+            if (row < chi) col[row] = (row < Kp && i < wdata) ? acc[r] : 0.f;
+        }
+    }
+}
+
 // Eigenvalues (even, odd) of the normalised Boltzmann matrix of one bond:
 // entries exp(beta*J*sx*sy - beta*|J|) are (1, x) or (x, 1) with
 // x = exp(-2 beta |J|), so lam = (1 + x, +-(1 - x)), sign of J.
@@ -895,7 +950,8 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     const int bst = (chi + 1) * ldt;  // one Tm / Wm block
 
     // ---- shared memory layout (see build_lds_bytes) ----------------------
-    const int regA_sz = 7 * CB * CB;                               // QR phase
+    const int VLb = CB <= 16 ? vrow_len<16>() : (CB <= 32 ? vrow_len<32>() : vrow_len<64>());
+    const int regA_sz = 3 * CB * CB + 2 * CB * VLb;                // QR phase
     // for chi <= 32 the SVD phase also holds the next site's Q slot, staged
     // by waves 2 and 3 while waves 0 and 1 run the Jacobi
     const bool qstage = CB <= 32;
@@ -904,7 +960,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     T *reg = reinterpret_cast<T *>(smem);
     T *C = reg;                       // [CB][CB]
     T *R = reg + CB * CB;             // [2][CB][CB]
-    T *Vh = reg + 3 * CB * CB;        // [2][CB][2CB] Householder vectors
+    T *Vh = reg + 3 * CB * CB;        // [2][CB][VLb] Householder vectors
     T *Tm = reg;                      // [2][chi+1][ldt]
     T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
     T *X = reg + 4 * bst;             // [2][chi][chi]
@@ -1167,7 +1223,14 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                     Tm[p * bst + idx * ldt + k] = acc;
                 }
                 };
-                if (qstage) tform(Qst); else tform(q);
+                // (the chi <= 32 kernels only: in the chi = 64 kernel the
+                // product's operands push the register allocation into spills)
+                if constexpr (std::is_same<T, float>::value && MAXB <= 32) {
+                    if (qstage) tform_mfma(Qst, X, Tm, chi, ldt, bst, K0, K1, r0, r1, mn0, mn1, n);
+                    else tform(q);
+                } else {
+                    if (qstage) tform(Qst); else tform(q);
+                }
             }
             if (tid < 8) jctl[tid] = (tid & 3) == 2 ? -1 : 0;   // {published, replayed, total, error}
             __syncthreads();
