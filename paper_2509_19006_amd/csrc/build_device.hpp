@@ -266,9 +266,12 @@ template <bool IL, typename T> __device__ __forceinline__ T from_prev(T v, int d
 // Both waves start from the columns ordered by decreasing norm (de Rijk's
 // pivoting, which shortens cyclic Jacobi), each computing the order from the
 // block.  On return the rotated block is back at Tb and W (n x n, same
-// leading dimension) at Wb.  Returns the sweep count (role 0).
+// leading dimension) at Wb, and the block wave writes the singular values
+// (column norms) of the positions to nrm_out[0, n): -1 for positions >= kr
+// and for an empty block.  Returns the sweep count (role 0).
 template <typename T, int CHI, bool IL, bool OFF>
-__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *ring, int *ctl) {
+__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *ring, int *ctl,
+                          T *nrm_out, int kr) {
     static_assert(!IL || CHI == 32, "the interleaved layout rotates 16-lane rows");
     constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G, RING = 2 * CHI;
     constexpr int WAIT_LIMIT = 1 << 22;   // polls of ~64 clocks: ~0.1 s
@@ -487,6 +490,17 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
     // after an odd number of sweeps the positions are reversed
     const bool rev = sweeps & 1;
     const int cx = rev ? CHI - 1 - 2 * g : 2 * g, cy = rev ? CHI - 2 - 2 * g : 2 * g + 1;
+    if (blk) {
+        // singular values from the registers (rows >= K hold zeros)
+        T sx[2] = {0, 0}, sy[2] = {0, 0};
+#pragma unroll
+        for (int i = 0; i < RK; ++i) { sx[i & 1] += x[i] * x[i]; sy[i & 1] += y[i] * y[i]; }
+        const T nx = pair_sum<IL>(sx[0] + sx[1], G), ny = pair_sum<IL>(sy[0] + sy[1], G);
+        if (gl == 0) {
+            if (cx < n) nrm_out[cx] = (cx < kr && K > 0) ? sqrt(nx) : (T)-1;
+            if (cy < n) nrm_out[cy] = (cy < kr && K > 0) ? sqrt(ny) : (T)-1;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
@@ -649,17 +663,18 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
 // four waves: waves 0 and 1 hold the blocks (role 0), waves 2 and 3 their
 // rotations W (role 1), for 16 < chi <= 32 through the rotation ring and
 // control words of the block (ring, ctl), for chi = 64 through prm and
-// flags; for chi <= 16 the block's wave carries W itself.
+// flags; for chi <= 16 the block's wave carries W itself.  For chi <= 32 the
+// block waves also write the singular values to nrm_out (see jacobi_reg).
 template <typename T, int MAXB>
 __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
-                            int *flags, T *ring, int *ctl) {
+                            int *flags, T *ring, int *ctl, T *nrm_out, int kr) {
     if constexpr (MAXB >= 64) {
         if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
     }
     // chi <= 16: contiguous groups, W in the block's wave; chi <= 32:
     // interleaved groups, W in a second wave
-    if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
-    return jacobi_reg<T, 32, true, true>(Tb, Wb, ld, K, n, lane, role, ring, ctl);
+    if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
+    return jacobi_reg<T, 32, true, true>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
 }
 
 // Sum over a lane's rows of a[r] * b[r] in four independent partial sums
@@ -1245,25 +1260,28 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 }
                 const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
                                                      tid & 63, wv >> 1, pb, jprm, jflag,
-                                                     jring + pb * 2 * CB * CB, jctl + 4 * pb);
+                                                     jring + pb * 2 * CB * CB, jctl + 4 * pb, nrm + pb * n, kr);
                 if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                 cyc_jac += wall_clock64() - t0;
             }
-            // singular values of both blocks (padding columns and empty blocks excluded)
-            for (int e = tid; e < 2 * n; e += NT) {
-                const int p = e / n, col = e % n, Kp = p ? K1 : K0;
-                const T *cp = Tm + p * bst + col * ldt;
-                T s2 = 0, s3 = 0;
-                if (col < kr) {
-                    int k = 0;
-                    for (; k + 1 < Kp; k += 2) { s2 += cp[k] * cp[k]; s3 += cp[k + 1] * cp[k + 1]; }
-                    if (k < Kp) s2 += cp[k] * cp[k];
+            // singular values of both blocks (padding columns and empty
+            // blocks excluded); for chi <= 32 the Jacobi wrote them
+            if (CB > 32) {
+                for (int e = tid; e < 2 * n; e += NT) {
+                    const int p = e / n, col = e % n, Kp = p ? K1 : K0;
+                    const T *cp = Tm + p * bst + col * ldt;
+                    T s2 = 0, s3 = 0;
+                    if (col < kr) {
+                        int k = 0;
+                        for (; k + 1 < Kp; k += 2) { s2 += cp[k] * cp[k]; s3 += cp[k + 1] * cp[k + 1]; }
+                        if (k < Kp) s2 += cp[k] * cp[k];
+                    }
+                    nrm[e] = (col < kr && Kp > 0) ? sqrt(s2 + s3) : (T)-1;
                 }
-                nrm[e] = (col < kr && Kp > 0) ? sqrt(s2 + s3) : (T)-1;
+                __syncthreads();
             }
-            __syncthreads();
             int kk = chi < K0 + K1 ? chi : K0 + K1;
             if (2 * kr < kk) kk = 2 * kr;
             // rank of every column over both blocks (ties by index); 2n is a
@@ -1271,6 +1289,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             for (int e = tid; e < 2 * n; e += NT) {
                 const T v = nrm[e];
                 int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+#pragma unroll 4
                 for (int o = 0; o < 2 * n; o += 4) {
                     const T w0 = nrm[o], w1 = nrm[o + 1], w2 = nrm[o + 2], w3 = nrm[o + 3];
                     q0 += (w0 > v) || (w0 == v && o < e);
@@ -1289,6 +1308,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                     const int p = e / n, re = rankv[e];
                     const int *rb = rankv + p * n;
                     int q0 = 0, q1 = 0;
+#pragma unroll 4
                     for (int o = 0; o < n; o += 2) { q0 += rb[o] < re; q1 += rb[o + 1] < re; }
                     colof[(p ? s0 : 0) + q0 + q1] = e;
                 }
