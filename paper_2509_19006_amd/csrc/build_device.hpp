@@ -802,10 +802,22 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
             x0 = group_sum(x0, G);
             T tj = 0, sc = 0, be = x0;
             if (s != (T)0) {
-                const T nr = sqrt(x0 * x0 + s);
-                be = x0 >= 0 ? -nr : nr;
-                tj = (be - x0) / be;
-                sc = (T)1 / (x0 - be);
+                const T nr2 = x0 * x0 + s;
+                // float: the hardware's 1-ulp square root and reciprocals
+                // when the column is well inside the normal range (then
+                // |be| and |x0 - be| >= |be| are too: be has the opposite
+                // sign of x0); they read denormal inputs as zero
+                if (std::is_same<T, float>::value && nr2 >= (T)4.7e-38f) {
+                    const T nr = path_sqrt(nr2);
+                    be = x0 >= 0 ? -nr : nr;
+                    tj = (be - x0) * fast_rcp(be);
+                    sc = fast_rcp(x0 - be);
+                } else {
+                    const T nr = sqrt(nr2);
+                    be = x0 >= 0 ? -nr : nr;
+                    tj = (be - x0) / be;
+                    sc = (T)1 / (x0 - be);
+                }
             }
 #pragma unroll
             for (int r = 0; r < RR; ++r) {
