@@ -973,6 +973,9 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     const size_t site_sz = (size_t)2 * cc2;
     const size_t row_sz = (size_t)L * site_sz;
     const int CB = chi <= 16 ? 16 : (chi <= 32 ? 32 : 64);   // compiled width holding chi
+    // per-site loops walk MAXB-wide index grids with shifts and masks (a
+    // division by a run-time width costs a dozen instructions or more)
+    constexpr int LB = MAXB <= 16 ? 4 : (MAXB <= 32 ? 5 : 6), MM = MAXB - 1;
     const int ldt = chi + 1;          // leading dim of Tm / Wm blocks (column-major)
     const int bst = (chi + 1) * ldt;  // one Tm / Wm block
 
@@ -1092,9 +1095,9 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 #pragma unroll
             for (int i = 0; i < CPT; ++i) {
                 const int e = tid + i * NT;
-                const int a = e / D, b = e % D;
+                const int a = e >> LB, b = e & MM;
                 const int n = (a >= pa0) ^ (b >= pb0);
-                pre[i] = e < Dp * D ? os[n * cc2 + a * chi + b] : (T)0;
+                pre[i] = (a < Dp && b < D) ? os[n * cc2 + a * chi + b] : (T)0;
             }
         };
         if constexpr (MAXB <= 32) fetch_site(0);
@@ -1110,8 +1113,8 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 #pragma unroll
                 for (int i = 0; i < CPT; ++i) {
                     const int e = tid + i * NT;
-                    if (e < Dp * D) {
-                        const int a = e / D, b = e % D;
+                    const int a = e >> LB, b = e & MM;
+                    if (a < Dp && b < D) {
                         const int n = (a >= pa0) ^ (b >= pb0);
                         C[a * CB + b] = (T)(n ? lv1 : lv0) * pre[i];
                     }
@@ -1124,15 +1127,15 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {
                     const int e = tid + i * NT;
-                    const int a = e / D, b = e % D;
+                    const int a = e >> LB, b = e & MM;
                     const int n = (a >= pa0) ^ (b >= pb0);
-                    v[i] = e < Dp * D ? os[n * cc2 + a * chi + b] : (T)0;
+                    v[i] = (a < Dp && b < D) ? os[n * cc2 + a * chi + b] : (T)0;
                 }
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {
                     const int e = tid + i * NT;
-                    if (e < Dp * D) {
-                        const int a = e / D, b = e % D;
+                    const int a = e >> LB, b = e & MM;
+                    if (a < Dp && b < D) {
                         const int n = (a >= pa0) ^ (b >= pb0);
                         C[a * CB + b] = (T)(n ? lv1 : lv0) * v[i];
                     }
@@ -1322,7 +1325,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                     int q0 = 0, q1 = 0;
 #pragma unroll 4
                     for (int o = 0; o < n; o += 2) { q0 += rb[o] < re; q1 += rb[o + 1] < re; }
-                    colof[(p ? s0 : 0) + q0 + q1] = e;
+                    colof[(p ? s0 : 0) + q0 + q1] = (p << 8) | (e - p * n);   // block, column
                 }
             }
             double kp = 0.0;
@@ -1330,11 +1333,12 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             const double nk = sqrt(block_sum(kp, red));   // (block_sum syncs)
             ls += log(nk);
             // new site c (right-canonical): slot a <- column colof[a]
-            for (int e = tid; e < cc2; e += NT) {
-                const int a = e / chi, m = e % chi;
+            for (int e = tid; e < MAXB * MAXB; e += NT) {
+                const int a = e >> LB, m = e & MM;
+                if (a >= chi || m >= chi) continue;
                 T v0 = 0, v1 = 0;
                 if (a < kk && m < kr) {
-                    const int ce = colof[a], p = ce / n, col = ce % n;
+                    const int ce = colof[a], p = ce >> 8, col = ce & 255;
                     const int pm = m >= r0, mm = pm ? m - r0 : m;
                     const int dp = p ? r1 : r0;
                     // physical parity s = p ^ pm; row of W^p for (s, m)
@@ -1349,7 +1353,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 // row-0 contraction from the right on the even physical component
                 double *u = uvec, *un = uvec + 64;
                 for (int a = tid; a < kk; a += NT) {
-                    const int ce = colof[a], p = ce / n, col = ce % n;
+                    const int ce = colof[a], p = ce >> 8, col = ce & 255;
                     double acc = 0.0;
                     // s = 0 entries: m in sector p, row = index within the sector
                     const int dp = p ? r1 : r0, off = p ? r0 : 0;
@@ -1370,12 +1374,12 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             __syncthreads();
             // X^p (K_p x d'^p) = U S / ||S_kept|| for the next site
             const T inv = (T)(1.0 / nk);
-            for (int e = tid; e < 2 * chi * chi; e += NT) {
-                const int p = e / cc2, k = (e / chi) % chi, j = e % chi;
+            for (int e = tid; e < 2 * MAXB * MAXB; e += NT) {
+                const int p = e >> (2 * LB), k = (e >> LB) & MM, j = e & MM;
                 const int Kp = p ? K1 : K0, dp = p ? kk - s0 : s0;
                 if (k < Kp && j < dp) {
                     const int ce = colof[(p ? s0 : 0) + j];
-                    X[e] = Tm[p * bst + (ce % n) * ldt + k] * inv;
+                    X[p * cc2 + k * chi + j] = Tm[p * bst + (ce & 255) * ldt + k] * inv;
                 }
             }
             if (tid == 0) { dsec[2 * c] = (unsigned char)s0; dsec[2 * c + 1] = (unsigned char)(kk - s0); }
