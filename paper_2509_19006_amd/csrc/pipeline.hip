@@ -36,16 +36,16 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
         if (d.chi <= 16) {
             sample_tile<T, S, 16, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
                                          spins_out, logq_out, nullptr, Jv_all, none,
-                                         reinterpret_cast<T(*)[16][16]>(smem), nullptr);
+                                         reinterpret_cast<typename StageType<T, S>::type(*)[16][16]>(smem), nullptr);
         } else if (MAXB <= 32 || d.chi <= 32) {
             sample_tile<T, S, 32, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
                                          spins_out, logq_out, nullptr, Jv_all, none,
-                                         reinterpret_cast<T(*)[32][32]>(smem), nullptr);
+                                         reinterpret_cast<typename StageType<T, S>::type(*)[32][32]>(smem), nullptr);
         } else {
             if constexpr (MAXB >= 64)
                 sample_tile<T, S, 64, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset,
                                              nullptr, spins_out, logq_out, nullptr, Jv_all, none,
-                                             reinterpret_cast<T(*)[64][64]>(smem), nullptr);
+                                             reinterpret_cast<typename StageType<T, S>::type(*)[64][64]>(smem), nullptr);
         }
         __syncthreads();
     }

@@ -14,7 +14,7 @@ k_sample(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws, size
     const int inst = blockIdx.y, tile = blockIdx.x;
     if (tile * NTS >= n_samples) return;
     const InstDesc d = desc[inst];
-    __shared__ T As[4][CHI][CHI];   // two staging buffers of both spin slices
+    __shared__ typename StageType<T, S>::type As[4][CHI][CHI];   // two staging buffers of both spin slices
     __shared__ float Ps[HAS_MLP ? MLP_NPARAM : 1];
     T *env = reinterpret_cast<T *>(ws + d.env_off + (size_t)tile * tile_bytes);
     sample_tile<T, S, CHI, HAS_MLP>(inst, tile, d, ws, env, n_samples, seed, sample_offset, forced, spins_out,

@@ -30,6 +30,17 @@ struct MlpArgs {
     const float *Jh;
 };
 
+// Element type of the staged sites in shared memory: a float16 cache stays
+// float16 there (half the LDS traffic of the broadcast reads that bound the
+// contractions; the conversion folds into the mixed-precision fma, and the
+// float each fma sees is the same), every other form is staged in T.
+template <typename T, typename S> struct StageType { using type = T; };
+template <> struct StageType<float, __half> { using type = __half; };
+template <typename T, typename ST> __device__ __forceinline__ T sget(ST v) {
+    if constexpr (std::is_same<T, ST>::value) return v;
+    else return __half2float(v);
+}
+
 // One tile of NTS samples of instance inst (all threads of the workgroup
 // call it).  env: the tile's right-environment scratch; As, Ps: shared
 // arrays for the staged site and the network weights.
@@ -38,10 +49,12 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                             int n_samples, uint64_t seed, uint64_t sample_offset,
                             const uint64_t *__restrict__ forced, uint64_t *spins_out,
                             double *__restrict__ logq_out, float *__restrict__ logits_out,
-                            const float *__restrict__ Jv_all, MlpArgs mlp, T (*As)[CHI][CHI], float *Ps) {
+                            const float *__restrict__ Jv_all, MlpArgs mlp,
+                            typename StageType<T, S>::type (*As)[CHI][CHI], float *Ps) {
     // no implicit multiply-add fusion: the sampler gives the same bits in
     // every kernel it is inlined into; the contractions fuse explicitly
 #pragma clang fp contract(off)
+    using ST = typename StageType<T, S>::type;
     const int tid = threadIdx.x;
     const int n = tile * NTS + tid;
     const bool act = n < n_samples;
@@ -80,11 +93,16 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
         }
     };
     auto put = [&](int buf) {
-        T *dst = &As[2 * buf][0][0];
+        ST *dst = &As[2 * buf][0][0];
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + i * NTS;
-            if (e < 2 * CHI * CHI) dst[e] = inb[i] ? load_as<T, S>(&pre[i]) : (T)0;
+            if (e < 2 * CHI * CHI) {
+                if constexpr (std::is_same<ST, S>::value && !std::is_same<ST, T>::value)
+                    dst[e] = inb[i] ? pre[i] : __float2half(0.f);
+                else
+                    dst[e] = inb[i] ? load_as<T, S>(&pre[i]) : (T)0;
+            }
         }
     };
 
@@ -107,7 +125,7 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
             for (int c = L - 2; c >= 0; --c) {
                 const bool more = c > 0;
                 if (more) fetch(crow + (size_t)c * site_sz);
-                T (*Ab)[CHI][CHI] = As + 2 * buf;
+                ST (*Ab)[CHI][CHI] = As + 2 * buf;
                 if (act) {
                 T w0 = 1, w1 = 1;
                 if (r > 0) {
@@ -125,7 +143,10 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 for (int a = 0; a < CHI; ++a) {
                     T z0 = 0, z1 = 0;
 #pragma unroll
-                    for (int b = 0; b < CHI; ++b) { z0 = fma(Ab[0][a][b], R[b], z0); z1 = fma(Ab[1][a][b], R[b], z1); }
+                    for (int b = 0; b < CHI; ++b) {
+                        z0 = fma(sget<T>(Ab[0][a][b]), R[b], z0);
+                        z1 = fma(sget<T>(Ab[1][a][b]), R[b], z1);
+                    }
                     Rn[a] = fma(w0, z0, w1 * z1);
                     mx = fmax(mx, fabs(Rn[a]));
                     __builtin_amdgcn_sched_barrier(0);
@@ -154,7 +175,7 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
             for (int c = 0; c < L; ++c) {
                 const bool more = c + 1 < L;
                 if (more) fetch(crow + (size_t)(c + 1) * site_sz);
-                T (*Ab)[CHI][CHI] = As + 2 * buf;
+                ST (*Ab)[CHI][CHI] = As + 2 * buf;
                 if (act) {
                 // y_s = l A_{c,s} for both spins; every staged value is read once
                 T y0[CHI], y1[CHI];
@@ -164,7 +185,10 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 for (int a = 0; a < CHI; ++a) {
                     const T la = l[a];
 #pragma unroll
-                    for (int b = 0; b < CHI; ++b) { y0[b] = fma(la, Ab[0][a][b], y0[b]); y1[b] = fma(la, Ab[1][a][b], y1[b]); }
+                    for (int b = 0; b < CHI; ++b) {
+                        y0[b] = fma(la, sget<T>(Ab[0][a][b]), y0[b]);
+                        y1[b] = fma(la, sget<T>(Ab[1][a][b]), y1[b]);
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 // rho_s = y_s . R_c  (R_{L-1} = e_0)
