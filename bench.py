@@ -32,8 +32,8 @@ PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}          # MI355X vector peaks, flop/
 # was measured on (sha256 over the files below), reported as null otherwise.
 TRAFFIC_SOURCES = ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
                    "paper_2509_19006_amd/csrc/device.hpp"]
-TRAFFIC = {"sha256": "4d9880668e0b8fd2918a9ae4869a237d393d2e8b73880b2eb15fc82ecd0408b6",
-           "bytes": 870259638970,
+TRAFFIC = {"sha256": "7f6b7f103b745bdca81dd31f95521ed47ada8a5154a8196d8bdc36a468e9a4c4",
+           "bytes": 870260078330,
            "profile": "profiles/k_build_k_sample_c3_fp16_hbm_traffic.txt"}
 
 

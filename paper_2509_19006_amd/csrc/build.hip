@@ -53,13 +53,13 @@ size_t build_lds_bytes(int chi, int L, size_t tsize) {
     const size_t vl = 2 * cb + (128 / cb - 1) * (cb >= 32 ? 4 : 0);   // padded Householder vector
     const size_t regA = 3 * cb * cb + 2 * cb * vl;
     const size_t regS = (size_t)4 * (chi + 1) * (chi + 1) + (size_t)2 * chi * chi +
-                        (cb <= 32 ? (size_t)4 * chi * chi + 4 * cb * cb : 0);   // + Q slot, rings
+                        (cb <= 32 ? (size_t)4 * chi * chi : 0);   // + staged Q slot
     size_t elems = (regA > regS ? regA : regS);
     elems += 2 * cb + 2 * (chi + 2) + 4 * cb;                 // tau, nrm, Jacobi rotations
     size_t bytes = elems * tsize;
     bytes = (bytes + 7) & ~(size_t)7;
     bytes += (NT / 64 + 128 + 8) * sizeof(double);           // red, uvec, scal
-    bytes += (2 * (2 * chi + 4) + 4 + 2 + 8) * sizeof(int);  // colof, rankv, iflag, jflag, jctl
+    bytes += (2 * (2 * chi + 4) + 4 + 2) * sizeof(int);      // colof, rankv, iflag, jflag
     bytes += (size_t)4 * (L + 1) + 4;                        // dsec, mq (+ alignment)
     bytes += (size_t)4 * 2 * L;                              // the row's couplings
     return (bytes + 15) & ~(size_t)15;

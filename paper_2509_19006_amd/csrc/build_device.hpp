@@ -660,21 +660,22 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
 // The register Jacobi for the smallest compiled width that holds chi; MAXB
 // is the widest one compiled into this kernel (wider paths only cost
 // registers, so a kernel carries the ones its launch needs).  Called by all
-// four waves: waves 0 and 1 hold the blocks (role 0), waves 2 and 3 their
-// rotations W (role 1), for 16 < chi <= 32 through the rotation ring and
-// control words of the block (ring, ctl), for chi = 64 through prm and
-// flags; for chi <= 16 the block's wave carries W itself.  For chi <= 32 the
-// block waves also write the singular values to nrm_out (see jacobi_reg).
+// four waves: waves 0 and 1 hold the blocks (role 0); for chi = 64 waves 2
+// and 3 carry their rotations W (role 1, through prm and flags), for
+// chi <= 32 the block's wave carries W itself.  For chi <= 32 the block
+// waves also write the singular values to nrm_out (see jacobi_reg).
 template <typename T, int MAXB>
 __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
                             int *flags, T *ring, int *ctl, T *nrm_out, int kr) {
     if constexpr (MAXB >= 64) {
         if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
     }
-    // chi <= 16: contiguous groups, W in the block's wave; chi <= 32:
-    // interleaved groups, W in a second wave
+    // chi <= 16: contiguous groups; chi <= 32: interleaved groups; W in the
+    // block's wave (the replay form, OFF, is not dispatched: with it the
+    // float64 build differed between runs at rounding level, so a published
+    // step count can be seen before the rotation values it covers)
     if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
-    return jacobi_reg<T, 32, true, true>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
+    return jacobi_reg<T, 32, true, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
 }
 
 // Sum over a lane's rows of a[r] * b[r] in four independent partial sums
@@ -985,8 +986,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     // for chi <= 32 the SVD phase also holds the next site's Q slot, staged
     // by waves 2 and 3 while waves 0 and 1 run the Jacobi
     const bool qstage = CB <= 32;
-    // and, for chi <= 32, the two blocks' Jacobi rotation rings
-    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 + 4 * CB * CB : 0);
+    const int regS_sz = 4 * bst + 2 * cc2 + (qstage ? 4 * cc2 : 0);
     T *reg = reinterpret_cast<T *>(smem);
     T *C = reg;                       // [CB][CB]
     T *R = reg + CB * CB;             // [2][CB][CB]
@@ -995,7 +995,6 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     T *Wm = reg + 2 * bst;            // [2][chi+1][ldt]
     T *X = reg + 4 * bst;             // [2][chi][chi]
     T *Qst = X + 2 * cc2;             // [2][2chi][chi] staged Q slot (chi <= 32)
-    T *jring = Qst + 4 * cc2;         // [2][2CB][CB/2][2] rotation rings (chi <= 32)
     T *tail = reg + (regA_sz > regS_sz ? regA_sz : regS_sz);
     T *tau = tail;                    // [2][CB]
     T *nrm = tau + 2 * CB;            // [2][chi+2]
@@ -1008,8 +1007,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     int *rankv = colof + 2 * chi + 4;                 // [2chi+4]
     int *iflag = rankv + 2 * chi + 4;                 // [4]
     int *jflag = iflag + 4;                           // [2] Jacobi: block still rotating
-    int *jctl = jflag + 2;                            // [2][4] Jacobi rotation streams
-    unsigned char *dsec = reinterpret_cast<unsigned char *>(jctl + 8);   // [L+1][2] bond sectors
+    unsigned char *dsec = reinterpret_cast<unsigned char *>(jflag + 2);  // [L+1][2] bond sectors
     unsigned char *mq = dsec + 2 * (L + 1);                            // [L+1][2] QR bond sectors
     // the current row's couplings (vertical, then horizontal)
     float *jrow = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(mq + 2 * (L + 1)) + 3) & ~(uintptr_t)3);
@@ -1262,7 +1260,6 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                     if (qstage) tform(Qst); else tform(q);
                 }
             }
-            if (tid < 8) jctl[tid] = (tid & 3) == 2 ? -1 : 0;   // {published, replayed, total, error}
             __syncthreads();
             {
                 const long long t0 = wall_clock64();
@@ -1275,7 +1272,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 }
                 const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
                                                      tid & 63, wv >> 1, pb, jprm, jflag,
-                                                     jring + pb * 2 * CB * CB, jctl + 4 * pb, nrm + pb * n, kr);
+                                                     nullptr, nullptr, nrm + pb * n, kr);
                 if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];

@@ -176,6 +176,16 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 const bool more = c + 1 < L;
                 if (more) fetch(crow + (size_t)(c + 1) * site_sz);
                 ST (*Ab)[CHI][CHI] = As + 2 * buf;
+                // chi <= 16: the site's right environment, read before the
+                // contraction so that its latency hides behind it (wider
+                // forms read it after: the registers cost them more)
+                constexpr bool PRE = CHI <= 16;
+                T renv[PRE ? CHI : 1];
+                if (PRE && act && c < L - 1) {
+                    const T *ec = env + (size_t)c * CHI * NTS + tid;
+#pragma unroll
+                    for (int b = 0; b < CHI; ++b) renv[b] = ec[(size_t)b * NTS];
+                }
                 if (act) {
                 // y_s = l A_{c,s} for both spins; every staged value is read once
                 T y0[CHI], y1[CHI];
@@ -195,6 +205,10 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                 T r0, r1;
                 if (c == L - 1) {
                     r0 = y0[0]; r1 = y1[0];
+                } else if constexpr (PRE) {
+                    r0 = 0; r1 = 0;
+#pragma unroll
+                    for (int b = 0; b < CHI; ++b) { r0 = fma(y0[b], renv[b], r0); r1 = fma(y1[b], renv[b], r1); }
                 } else {
                     const T *ec = env + (size_t)c * CHI * NTS + tid;
                     r0 = 0; r1 = 0;
