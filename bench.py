@@ -32,7 +32,7 @@ PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}          # MI355X vector peaks, flop/
 # was measured on (sha256 over the files below), reported as null otherwise.
 TRAFFIC_SOURCES = ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
                    "paper_2509_19006_amd/csrc/device.hpp"]
-TRAFFIC = {"sha256": "7f6b7f103b745bdca81dd31f95521ed47ada8a5154a8196d8bdc36a468e9a4c4",
+TRAFFIC = {"sha256": "e934049df3328d5f7e2e9a1202f3601e92499ed3f98c4e996ba97a901a385582",
            "bytes": 870260078330,
            "profile": "profiles/k_build_k_sample_c3_fp16_hbm_traffic.txt"}
 

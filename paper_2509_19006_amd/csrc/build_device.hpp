@@ -672,8 +672,9 @@ __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lan
     }
     // chi <= 16: contiguous groups; chi <= 32: interleaved groups; W in the
     // block's wave (the replay form, OFF, is not dispatched: with it the
-    // float64 build differed between runs at rounding level, so a published
-    // step count can be seen before the rotation values it covers)
+    // float64 build differed between runs at rounding level, also with
+    // release / acquire fences around the published count, for a reason
+    // not yet found)
     if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
     return jacobi_reg<T, 32, true, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
 }
