@@ -5,13 +5,14 @@ Test infrastructure only: nothing in the product path imports this module.
 Follows section 3.2 (cache initialization) and section 2.2 (Eqs. (6)-(8),
 Fig. 2) step by step, with plain dense tensors:
 
-1. bottom row L-1: copy tensors combined with that row's horizontal
-   Boltzmann matrices give a bond-dimension-2 MPS (site shapes (1,2,2),
-   (2,2,2), ..., (2,2,1));
-2. for each row r = L-2 ... 0: build the row MPO from copy tensors and the
-   row's right/down Boltzmann matrices (index order left, phys, right, down;
-   shapes (1,2,2,2), (2,2,2,2), ..., (2,2,1,2)); apply it to the MPS
-   ("multiply", which doubles the bond); truncate back to chi ("compress").
+1. bottom row L-1: the product of that row's horizontal Boltzmann weights
+   as a bond-dimension-2 MPS, every bond carrying the spin its Boltzmann
+   matrix passes on (site shapes (1,2,2), (2,2,2), ..., (2,2,1));
+2. for each row r = L-2 ... 0: the row's transfer operator as an MPO whose
+   entries are written out from Eqs. (7)-(8) (index order left, own spin,
+   right, lower spin; shapes (1,2,2,2), (2,2,2,2), ..., (2,2,1,2)); apply it
+   to the MPS ("multiply", which doubles the bond); truncate back to chi
+   ("compress").
 
 ``compress`` is not listed in the paper; the reading used here (and by the
 GPU path) is: a left-to-right QR sweep that makes every site left-canonical
@@ -29,6 +30,8 @@ vertical bond below row r (exactly when chi >= 2**floor(L/2)).
 Pins (tests/test_oracle_bmps.py): brute-force ln Z on 3x3/4x4, the dense
 transfer vector (exact and with the same sequential truncation) on L <= 10,
 closed forms (J_v = 0, J_h = 0, beta = 0) at large L, Z2 and gauge invariance.
+The cut diagnostic of compress is pinned on states with a prescribed
+Schmidt spectrum (tests/test_oracle_exact.py).
 """
 from __future__ import annotations
 
@@ -39,27 +42,41 @@ import numpy as np
 from .ising import boltzmann_matrix
 
 
-def copy_tensor(rank: int) -> np.ndarray:
-    """Eq. (8): the Kronecker delta with `rank` legs of dimension 2."""
-    t = np.zeros((2,) * rank)
-    for i in range(2):
-        t[(i,) * rank] = 1.0
-    return t
-
-
 def _normalise(t: np.ndarray):
     nu = float(np.linalg.norm(t))
     return t / nu, math.log(nu)
 
 
+def _bond_dims(L: int, c: int):
+    """(left, right) bond dimensions of column c in a bond-2 row network:
+    the open ends carry a trivial index of dimension 1."""
+    return (1 if c == 0 else 2), (1 if c == L - 1 else 2)
+
+
 def bottom_row_mps(beta: float, J_h: np.ndarray):
-    """Row L-1 of the cache, bond dimension 2 (section 3.2)."""
+    """Row L-1 of the cache, bond dimension 2 (section 3.2).
+
+    The bottom row's function of its spins is the product of its horizontal
+    Boltzmann weights (Eq. 7), psi(s) = prod_c B(J_h[L-1, c])[s_c, s_{c+1}].
+    Written as an MPS, the bond between columns c and c+1 carries the spin
+    reached through that bond's Boltzmann matrix, and the copy tensor of
+    Eq. (8) at column c+1 forces it to equal s_{c+1}:
+
+        A_c[a, s, b] = [c == 0 or a == s] * (B_c[s, b] if c < L-1 else 1).
+    """
     L = J_h.shape[0]
-    I2, I3 = np.eye(2), copy_tensor(3)
-    mps = [(I2 @ boltzmann_matrix(beta, J_h[L - 1, 0]))[None]]            # (1, 2, 2)
-    for c in range(1, L - 1):
-        mps.append(np.einsum("ask,kb->asb", I3, boltzmann_matrix(beta, J_h[L - 1, c])))
-    mps.append(I2[:, :, None])                                             # (2, 2, 1)
+    mps = []
+    for c in range(L):
+        Dl, Dr = _bond_dims(L, c)
+        Bh = boltzmann_matrix(beta, J_h[L - 1, c]) if c < L - 1 else None
+        A = np.zeros((Dl, 2, Dr))
+        for a in range(Dl):
+            for s in range(2):
+                if c > 0 and a != s:
+                    continue                      # copy tensor: left bond = own spin
+                for b in range(Dr):
+                    A[a, s, b] = Bh[s, b] if Bh is not None else 1.0
+        mps.append(A)
     # Scale each site to unit norm; the state changes only by a positive
     # factor, which is kept in the log-scale.
     logscale = 0.0
@@ -70,22 +87,37 @@ def bottom_row_mps(beta: float, J_h: np.ndarray):
 
 
 def row_mpo(beta: float, J_h: np.ndarray, J_v: np.ndarray, row: int):
-    """Row MPO from copy tensors and Boltzmann matrices (section 3.2).
+    """Transfer MPO of one row (section 3.2, Eqs. 7-8).
 
-    Index order (left, phys, right, down).  The right leg carries the
-    horizontal Boltzmann matrix to the next column, the down leg the vertical
-    one to the row below.
+    The row's spins s_c interact with their right neighbours through
+    B(J_h[row, c]) and with the spins n_c of the row below through
+    B(J_v[row, c]).  As an operator from the lower row's spins n to the
+    row's own spins s, with a bond index carrying s_c's horizontal weight to
+    column c+1 (where the copy tensor makes it equal s_{c+1}):
+
+        W_c[l, s, r, n] = [c == 0 or l == s]
+                          * (B(J_h[row, c])[s, r] if c < L-1 else 1)
+                          * B(J_v[row, c])[s, n].
+
+    Index order (left, own spin, right, lower spin); the open ends have
+    dimension 1.
     """
     L = J_h.shape[0]
-    I3, I4 = copy_tensor(3), copy_tensor(4)
     mpo = []
-    Br, Bd = boltzmann_matrix(beta, J_h[row, 0]), boltzmann_matrix(beta, J_v[row, 0])
-    mpo.append(np.einsum("ijk,jl,km->ilm", I3, Br, Bd)[None])              # (1, 2, 2, 2)
-    for c in range(1, L - 1):
-        Br, Bd = boltzmann_matrix(beta, J_h[row, c]), boltzmann_matrix(beta, J_v[row, c])
-        mpo.append(np.einsum("ijkl,km,ln->ijmn", I4, Br, Bd))              # (2, 2, 2, 2)
-    Bd = boltzmann_matrix(beta, J_v[row, L - 1])
-    mpo.append(np.einsum("ijk,kl->ijl", I3, Bd)[:, :, None, :])            # (2, 2, 1, 2)
+    for c in range(L):
+        Dl, Dr = _bond_dims(L, c)
+        Bh = boltzmann_matrix(beta, J_h[row, c]) if c < L - 1 else None
+        Bv = boltzmann_matrix(beta, J_v[row, c])
+        W = np.zeros((Dl, 2, Dr, 2))
+        for l in range(Dl):
+            for s in range(2):
+                if c > 0 and l != s:
+                    continue
+                for r in range(Dr):
+                    h = Bh[s, r] if Bh is not None else 1.0
+                    for n in range(2):
+                        W[l, s, r, n] = h * Bv[s, n]
+        mpo.append(W)
     return mpo
 
 

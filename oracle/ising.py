@@ -7,8 +7,7 @@ Test infrastructure only: nothing in the product path imports this module.
 * Boltzmann matrix, Eq. (7) of section 2.2: B[a, b] = exp(beta * J * s_a * s_b)
   with index 0 <-> spin -1 and index 1 <-> spin +1 (the sampler of section 3.3
   maps a stored bit x to the spin 2x - 1).
-* Conversion to the paper's per-site coupling tensor J_mat (L, L, 4) with
-  k = (left, up, right, down) and zeros on open boundaries (section 3.1).
+* Spin packing into the 64-bit words the GPU path reads and writes.
 """
 from __future__ import annotations
 
@@ -33,17 +32,6 @@ def energy(spins: np.ndarray, J_h: np.ndarray, J_v: np.ndarray) -> np.ndarray:
     eh = (jh * s[..., :, :-1] * s[..., :, 1:]).sum(axis=(-1, -2))
     ev = (jv * s[..., :-1, :] * s[..., 1:, :]).sum(axis=(-1, -2))
     return -(eh + ev)
-
-
-def to_jmat(J_h: np.ndarray, J_v: np.ndarray) -> np.ndarray:
-    """Per-site (left, up, right, down) couplings, zero on open boundaries."""
-    L = J_h.shape[0]
-    jm = np.zeros((L, L, 4), dtype=np.float64)
-    jm[:, 1:, 0] = J_h          # left neighbour of (r, c) is (r, c-1)
-    jm[1:, :, 1] = J_v          # up neighbour of (r, c) is (r-1, c)
-    jm[:, :-1, 2] = J_h         # right
-    jm[:-1, :, 3] = J_v         # down
-    return jm
 
 
 def bits_to_spins(bits: np.ndarray) -> np.ndarray:

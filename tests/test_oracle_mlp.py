@@ -85,3 +85,36 @@ def test_features_window():
     x = mlp.features(s, jh, jv, np.zeros(2), 3, 4)
     assert np.array_equal(x[:, 40:45], s[:, 1, 2:7]) and np.array_equal(x[:, 50:52], s[:, 3, 2:4])
     assert np.all(x[:, 53:] == 0)
+
+
+def test_adam_first_step_is_bias_corrected_sign_step():
+    """With the default b1, b2 the bias-corrected first moments equal g and
+    g**2 exactly, so step 1 moves every weight by lr * g / (|g| + eps)
+    (Kingma & Ba, Alg. 1) -- a missing or wrong correction changes it by
+    factors of 10 (1 - b1) or 30 (sqrt(1 - b2))."""
+    p = {"w": np.array([0.25, -1.5, 2.0, 0.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3, 2.0])}
+    m = {"w": np.zeros(4)}
+    v = {"w": np.zeros(4)}
+    mlp.adam_step(p, g, m, v, step=1, lr=0.01)
+    want = np.array([0.25, -1.5, 2.0, 0.0]) - 0.01 * g["w"] / (np.abs(g["w"]) + 1e-8)
+    assert np.allclose(p["w"], want, rtol=0, atol=1e-15)
+
+
+def test_adam_second_step_by_hand():
+    """Step 2 with gradients g1 = 1, g2 = 3 on one weight, the moments and
+    the update worked out by hand from Kingma & Ba's Algorithm 1."""
+    p = {"w": np.array([1.0])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    lr, b1, b2, eps = 0.1, 0.9, 0.999, 1e-8
+    mlp.adam_step(p, {"w": np.array([1.0])}, m, v, 1, lr)
+    mlp.adam_step(p, {"w": np.array([3.0])}, m, v, 2, lr)
+    # m2 = 0.9 * 0.1 + 0.1 * 3 = 0.39;  v2 = 0.999 * 0.001 + 0.001 * 9 = 0.009999
+    # mh = 0.39 / (1 - 0.81) = 2.0526315789...;  vh = 0.009999 / (1 - 0.998001) = 5.0020010005...
+    m2, v2 = 0.39, 0.009999
+    mh, vh = m2 / 0.19, v2 / 0.001999
+    want = 1.0 - lr / (1.0 + eps) - lr * mh / (np.sqrt(vh) + eps)
+    assert abs(m["w"][0] - m2) < 1e-15 and abs(v["w"][0] - v2) < 1e-15
+    assert abs(p["w"][0] - want) < 1e-14
+    assert abs(p["w"][0] - 0.8082219) < 1e-6
