@@ -3,16 +3,23 @@
 
 One step = the whole path over one batch of synthetic disorders: boundary-MPS
 cache build (tnmc_build_env), sampling (tnmc_sample), exact energies
-(tnmc_energy) and the Metropolis independence step (tnmc_accept), all on one
-stream with the couplings already resident in HBM.  Workload (default): the
-mixed-precision configuration -- 256 x 256 open-boundary +-J Edwards-Anderson
-lattices, beta = 1, chi = 32, 256 disorders x 256 samples; the same inputs are
-also run through the plain float32 path.  The Markov chains continue across
-steps; accepted samples are accepted Metropolis trials.
+(tnmc_energy, float64 and int32) and the Metropolis independence step
+(tnmc_accept), all on one stream with the couplings already resident in HBM.
+Default workload: 256 x 256 open-boundary +-J Edwards-Anderson lattices,
+beta = 1, chi = 32, 256 disorders x 256 samples, run through the plain
+float32 path (the headline value) and through the float16-stored-cache form
+on the same inputs.  The Markov chains continue across steps; accepted
+samples are accepted Metropolis trials.
 
-Prints one JSON line (rank 0) with the headline value (mixed form), the plain
-float32 comparison, a roofline entry for the dominant kernel (the cache
-build) and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line with the headline value, both forms, a roofline entry
+for the dominant kernel (the cache build) and one per form for the sampler,
+and the CPU oracle run end to end on one instance of the workload in a child
+process while the GPU forms run.
+
+Other workloads (--workload): uneven (the 512-instance mix in one persistent
+launch), learned (the learned proposal correction), paper (the paper's
+1024 x 1024 +-J run at chi = 8, disorder-chunked) and sweep (acceptance
+against L, chi and beta).
 """
 from __future__ import annotations
 
@@ -24,7 +31,9 @@ import sys
 import time
 
 METRIC = "accepted samples/s at L=256 chi=32 + acceptance rate, learned/mixed vs plain"
-PEAK = {"fp32": 157.3e12, "fp64": 78.6e12}          # MI355X vector peaks, flop/s
+# MI355X published peaks: vector float32 / float64 flop/s, dense bf16/fp16
+# MFMA flop/s, HBM bytes/s
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "mfma16": 2.5e15, "hbm": 8.0e12}
 
 # HBM traffic of one cache-build launch at the default workload, from two
 # rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
@@ -53,22 +62,52 @@ def traffic_for_current_kernel():
     return TRAFFIC["bytes"] if h.hexdigest() == TRAFFIC["sha256"] else None
 
 
-def build_flops_model(L, chi, B):
-    """Algorithmic flops of one cache build: per site of every row above the
-    bottom one, 32 chi^2 + (101 + 48 S) chi^3 with S = 8 Jacobi sweeps (the
-    dense boundary-MPS cost model: MPO apply, QR sweep, SVD sweep)."""
+def build_flops_dense(L, chi, B):
+    """Flops of one cache build under the dense boundary-MPS cost model: per
+    site of every row above the bottom one, 32 chi^2 + (101 + 48 S) chi^3
+    with S = 8 Jacobi sweeps (dense MPO apply, 4chi x 2chi QR with explicit
+    Q, 2chi x 2chi one-sided Jacobi).  A reference figure only: the kernel
+    does not execute this work."""
     per_site = 32 * chi ** 2 + (101 + 48 * 8) * chi ** 3
     return B * (L - 1) * L * per_site
 
 
+def build_flops_executed(L, chi, B, sweeps_per_site):
+    """Flops the spin-flip (Z2) symmetric kernel executes in one cache build:
+    per bulk site-row two parity blocks, each a 2chi x chi Householder QR with
+    its explicit Q (2 x 10/3 chi^3), the carried-R product of a chi x chi by
+    a chi x 2chi block (4 chi^3), the chi x chi centre T = Q X (2 chi^3) and
+    the one-sided Jacobi on a chi x chi block at 7 chi^3 per sweep (chi^2/2
+    pairs, each one dot product and two column rotations of length chi plus
+    the two rotated columns of W); with S the measured sweeps per site this
+    is (2 chi^2 +) (25.3 + 14 S) chi^3 per site-row, the O(chi^2) apply
+    included."""
+    per_site = 2 * chi ** 2 + (2 * (20.0 / 3 + 4 + 2)) * chi ** 3 + 14.0 * sweeps_per_site * chi ** 3
+    return B * (L - 1) * L * per_site
+
+
+def sample_flops(L, chi, B, N):
+    """Algorithmic flops of one sampling pass: 8 chi^2 per site-sample (left
+    product l A_s for both spins and the right-environment product, 2 chi^2
+    multiply-adds each)."""
+    return 8 * chi ** 2 * L * L * B * N
+
+
+def sample_bytes(L, chi, B, N, cache_elem_bytes):
+    """Algorithmic HBM bytes of one sampling pass: the cache read once
+    (2 chi^2 entries per site) and the packed spins written once."""
+    return B * L * L * 2 * chi ** 2 * cache_elem_bytes + B * N * L * ((L + 63) // 64) * 8
+
+
 def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed):
-    problem = T.Problem(jh, jv, [L] * B, chi, beta)
+    problem = T.Problem(jh, jv, [L] * B, chi, beta, coupling_kind=T.COUPLING_PMJ)
     nbytes = T.tnmc_workspace_size(problem, prec, N)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     words = N * problem.spin_words_per_sample()
     spins = torch.empty(words, dtype=torch.int64, device="cuda")
     logq = torch.empty((B, N), dtype=torch.float64, device="cuda")
     E = torch.empty((B, N), dtype=torch.float64, device="cuda")
+    E_int = torch.empty((B, N), dtype=torch.int32, device="cuda")
     acc = torch.empty((B, N), dtype=torch.uint8, device="cuda")
     chain = torch.zeros(B * T.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
     beta_t = torch.full((B,), float(beta), dtype=torch.float64, device="cuda")
@@ -83,7 +122,7 @@ def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed):
         if marks: marks[1].record(stream)
         T.tnmc_sample(env, N, seed, spins, logq, sample_offset=k * N)
         if marks: marks[2].record(stream)
-        T.tnmc_energy(env, N, spins, E)
+        T.tnmc_energy(problem, N, spins, E, E_int)
         if marks: marks[3].record(stream)
         T.tnmc_accept(logq, E, beta_t, chain, seed, k * N, acc)
         if marks: marks[4].record(stream)
@@ -107,55 +146,79 @@ def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed):
     n_tr = sum(s["n_trials"] for s in st)
     phase = [sum(ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)) / steps for i in range(4)]
     stats = T.tnmc_env_stats(envs[-1])
+    T.tnmc_env_check(envs[-1])           # raises on a non-finite log-scale / unconverged Jacobi
+    assert torch.equal(E_int.double(), E), "int32 and float64 energies differ"
     out = dict(value=n_acc / wall, acceptance=n_acc / max(1, n_tr), accepted=n_acc, trials=n_tr,
                wall_s=wall, ms_per_step=1e3 * wall / steps,
                build_ms=phase[0], sample_ms=phase[1], energy_ms=phase[2], accept_ms=phase[3],
                jacobi_sweeps_per_site=float(stats[:, 0].mean()) / ((L - 1) * L),
+               mean_energy_per_spin=float(E.mean().item()) / (L * L),
                logz_mean=float(logz.mean().item()))
     del envs, ws
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(L, chi, beta, N, acceptance, jh, jv, build_rows=36, sample_rows=3, n_sample=8):
-    """The oracle, timed on a bounded sample of one instance of the workload:
-    `build_rows` bulk rows of the cache build (after the bonds have reached
-    chi) and `sample_rows` rows of sampling for `n_sample` samples, scaled to
-    a whole instance (L-1 rows built, N samples of L rows)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_child(L, chi, beta, n_sample):
+    """The oracle end to end on one instance of the workload (the first
+    disorder of the batch): the float64 cache build of all L - 1 rows,
+    n_sample draws, their energies and the Metropolis chain over them.
+    Prints one JSON line; runs in a child process beside the GPU forms."""
     import numpy as np
-    from oracle import bmps, sampler
+    import workloads
+    from oracle import bmps, ising, mis, sampler
     try:
         from threadpoolctl import threadpool_info
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         cores = len(os.sched_getaffinity(0))
-    jh = jh.astype(np.float64)
-    jv = jv.astype(np.float64)
-    mps, _ = bmps.bottom_row_mps(beta, jh)
-    row = L - 2
-    for _ in range(int(math.log2(chi)) + 2):                 # bonds grow to chi
-        mps = bmps.multiply(bmps.row_mpo(beta, jh, jv, row), mps)
-        _, mps = bmps.compress(mps, chi)
-        row -= 1
+    jh, jv = workloads.batch(L, 1, "pmj", 3)
+    jh, jv = jh[0].astype(np.float64), jv[0].astype(np.float64)
     t0 = time.perf_counter()
-    for _ in range(build_rows):
-        mps = bmps.multiply(bmps.row_mpo(beta, jh, jv, row), mps)
-        _, mps = bmps.compress(mps, chi)
-        row -= 1
-    t_row = (time.perf_counter() - t0) / build_rows
-    rng = np.random.default_rng(0)
-    u = rng.integers(0, 2, (n_sample, L))
-    t0 = time.perf_counter()
-    for _ in range(sample_rows):
-        sampler.sample_row(mps, beta, jv[row], u, n_sample, uniforms=rng.random((n_sample, L)))
-    t_srow = (time.perf_counter() - t0) / (sample_rows * n_sample)
-    per_instance = (L - 1) * t_row + N * L * t_srow
-    return {"value": acceptance * N / per_instance, "unit": "accepted samples/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": (f"one {L}x{L} chi={chi} instance: {build_rows} bulk rows of the float64 cache "
-                       f"build ({t_row:.3f} s/row) and {sample_rows} rows x {n_sample} samples of "
-                       f"sampling ({t_srow * 1e3:.2f} ms per sample-row), scaled to {L - 1} rows and "
-                       f"{N} samples; acceptance taken from the float32 GPU run")}
+    cache, _, _ = bmps.build_cache(beta, jh, jv, chi)
+    t_build = time.perf_counter() - t0
+    bits, logq, _ = sampler.sample(cache, beta, jv, n_sample, seed=0x5A5A0003)
+    E = ising.energy(2 * bits - 1, jh, jv)
+    chain = mis.Chain()
+    mis.accept(logq, E, beta, chain, 0x5A5A0003, 0, 0)
+    wall = time.perf_counter() - t0
+    print(json.dumps({"value": chain.n_acc / wall, "unit": "accepted samples/s", "cores": int(cores),
+                      "kind": "oracle", "cpu": cpu_model(),
+                      "acceptance": chain.n_acc / max(1, chain.n_trials), "trials": chain.n_trials,
+                      "wall_s": wall, "build_s": t_build,
+                      "sample": (f"one {L}x{L} +-J instance of the workload (chi={chi}, beta={beta}): the "
+                                 f"float64 cache build of all {L - 1} rows ({t_build:.1f} s), {n_sample} "
+                                 f"draws, their energies and the oracle's own Metropolis chain "
+                                 f"({chain.n_acc} of {chain.n_trials} trials accepted), timed end to end")}),
+          flush=True)
+
+
+def start_cpu_baseline(L, chi, beta, n_sample=8):
+    """Starts the oracle leg as a child process before this process touches
+    the GPU; collect it with finish_cpu_baseline."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--L", str(L), "--chi", str(chi),
+           "--beta", str(beta), "--samples", str(n_sample)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)
+
+
+def finish_cpu_baseline(proc):
+    out, _ = proc.communicate()
+    if proc.returncode != 0:
+        log(f"cpu baseline failed with status {proc.returncode}")
+        return None
+    return json.loads(out.strip().splitlines()[-1])
 
 
 def c4_spec():
@@ -311,10 +374,11 @@ def main():
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--beta", type=float, default=1.0)
     ap.add_argument("--mixed", choices=["bf16", "fp16"], default="fp16")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain float32 comparison")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the stored-cache comparison form")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["mixed", "uneven", "learned"], default="mixed",
-                    help="mixed: the headline 256x256 batch (default); uneven: the 512-instance mix in one "
+    ap.add_argument("--workload", choices=["headline", "uneven", "learned"], default="headline",
+                    help="headline: the 256x256 batch (default); uneven: the 512-instance mix in one "
                          "persistent launch with an autotuned schedule; learned: the learned correction "
                          "(use with --L 1024 --disorders 64 --samples 16)")
     ap.add_argument("--train-L", type=int, default=256, help="learned: side of the training lattices")
@@ -326,11 +390,18 @@ def main():
                     help="only run a plain device-to-device copy of this many GiB three times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.L, args.chi, args.beta, args.samples)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the instances are independent and this build runs "
               "on a single MI355X; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    cpu_proc = None
+    if args.workload == "headline" and not args.no_cpu_baseline:
+        # the oracle leg runs on the host cores while the GPU forms run
+        cpu_proc = start_cpu_baseline(args.L, args.chi, args.beta)
     import numpy as np
     import torch
     if args.copy_probe > 0:
@@ -360,43 +431,64 @@ def main():
     seed = 0x5A5A0003
 
     mixed_prec = T.MIXED_BF16 if args.mixed == "bf16" else T.MIXED_FP16
-    log(f"mixed form ({args.mixed} cache, float32 build):")
-    mixed = run_form(T, torch, mixed_prec, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
-    plain = None
-    if not args.no_plain:
-        log("plain float32 form:")
-        plain = run_form(T, torch, T.FP32, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+    log("plain float32 form:")
+    plain = run_form(T, torch, T.FP32, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+    mixed = None
+    if not args.no_mixed:
+        log(f"stored-cache form ({args.mixed} cache, float32 build):")
+        mixed = run_form(T, torch, mixed_prec, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
 
-    flops = build_flops_model(L, chi, B)
-    achieved = flops / (mixed["build_ms"] * 1e-3)
+    # the dominant kernel: the cache build (float32 vector ALU, latency bound)
+    S = plain["jacobi_sweeps_per_site"]
+    ex = build_flops_executed(L, chi, B, S)
+    dense = build_flops_dense(L, chi, B)
+    t_build = plain["build_ms"] * 1e-3
     roof = {"bound": "alu", "kernel": "k_build (cache build, float32 arithmetic)",
-            "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK["fp32"],
-            "traffic": (traffic_for_current_kernel()
-                        if (L, chi, B, args.mixed) == (256, 32, 256, "fp16") else None),
-            "flops_per_launch": flops,
-            "per_unit": "32 chi^2 + 485 chi^3 flop per site-row (dense cost model, 8 sweeps)",
-            "units_per_launch": B * (L - 1) * L}
+            "achieved": ex / t_build / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+            "frac": ex / t_build / PEAK["fp32"],
+            "traffic": traffic_for_current_kernel() if (L, chi, B) == (256, 32, 256) else None,
+            "flops_per_launch": ex,
+            "per_unit": (f"(2 chi^2 +) (25.3 + 14 S) chi^3 flop per site-row executed by the parity-block "
+                         f"kernel, S = {S:.2f} measured Jacobi sweeps per site"),
+            "units_per_launch": B * (L - 1) * L,
+            "dense_model": {"flops_per_launch": dense, "achieved": dense / t_build / 1e12,
+                            "frac": dense / t_build / PEAK["fp32"],
+                            "per_unit": "32 chi^2 + 485 chi^3 flop per site-row (dense 2chi blocks, 8 sweeps); "
+                                        "not the work the kernel executes"}}
+    # the sampler, by form: algorithmic flops and bytes against the roof its
+    # intensity selects
+    roof_sample = {}
+    for name, f, eb, peak, pname in (("plain_fp32", plain, 4, PEAK["fp32"], "fp32 vector/MFMA"),
+                                     (f"mixed_{args.mixed}", mixed, 2, PEAK["mfma16"], "bf16/fp16 MFMA dense")):
+        if f is None:
+            continue
+        fl, by = sample_flops(L, chi, B, N), sample_bytes(L, chi, B, N, eb)
+        t = f["sample_ms"] * 1e-3
+        ridge = peak / PEAK["hbm"]
+        bound_hbm = fl / by < ridge
+        roof_sample[name] = {
+            "kernel": "k_sample", "bound": "hbm" if bound_hbm else "mfma",
+            "achieved": (by / t / 1e9) if bound_hbm else (fl / t / 1e12),
+            "peak": (PEAK["hbm"] / 1e9) if bound_hbm else (peak / 1e12),
+            "unit": "GB/s" if bound_hbm else "TFLOP/s",
+            "frac": (by / t / PEAK["hbm"]) if bound_hbm else (fl / t / peak),
+            "flops_per_launch": fl, "algorithmic_bytes": by, "intensity_flop_per_byte": fl / by,
+            "peak_kind": pname, "traffic": None}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        acc_ref = (plain or mixed)["acceptance"]
-        cpu = cpu_baseline(L, chi, beta, N, acc_ref, jh_np[0], jv_np[0])
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc is not None else None
 
     line = {
-        "metric": METRIC, "value": mixed["value"], "unit": "accepted samples/s",
+        "metric": METRIC, "value": plain["value"], "unit": "accepted samples/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": mixed["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": plain["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": (f"mixed-precision TNMC: {L}x{L} open +-J EA lattices, beta={beta}, "
-                                f"chi={chi}, {B} disorders x {N} samples, {args.mixed} cache, float32 "
-                                "build, float64 log-weights and accept"),
-                   "L": L, "chi": chi, "disorders": B, "samples": N, "beta": beta,
-                   "form": f"mixed-{args.mixed}"},
-        "acceptance": mixed["acceptance"],
-        "mixed": mixed, "plain_fp32": plain,
-        "roofline": roof, "cpu_baseline": cpu,
+        "config": {"workload": (f"TNMC on {L}x{L} open +-J EA lattices, beta={beta}, chi={chi}, {B} disorders x "
+                                f"{N} samples: float32 build and sampler, float64 log-weights and accept, int32 "
+                                f"energies; beside it the {args.mixed}-stored-cache form on the same inputs"),
+                   "L": L, "chi": chi, "disorders": B, "samples": N, "beta": beta, "form": "plain-fp32"},
+        "acceptance": plain["acceptance"],
+        "plain_fp32": plain, f"mixed_{args.mixed}": mixed,
+        "roofline": roof, "roofline_sample": roof_sample, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

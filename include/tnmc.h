@@ -56,14 +56,24 @@ extern "C" {
 #define TNMC_ENOSPACE -2   /* workspace smaller than tnmc_workspace_size    */
 #define TNMC_EHIP     -3   /* HIP runtime or launch error                   */
 #define TNMC_ENOTSUP  -4   /* precision / size combination not built        */
+#define TNMC_ENUMERIC -5   /* NaN / Inf in a log-scale, or a Jacobi SVD that
+                              stopped at its sweep limit (tnmc_env_check)   */
 
 /* ---- precision of the boundary-MPS build and of the sampler ----------- */
 #define TNMC_FP64        0 /* everything in float64                          */
 #define TNMC_FP32        1 /* contractions, QR, SVD and cache in float32;    */
                            /* log-weights, log q and accept in float64       */
-#define TNMC_MIXED_BF16  2 /* build in float32, cache stored in bfloat16,   */
-                           /* sampler contractions bf16 x bf16 -> float32    */
+#define TNMC_MIXED_BF16  2 /* build in float32, cache stored in bfloat16;   */
+                           /* the sampler widens each stored entry to float32 */
+                           /* and contracts in float32                       */
 #define TNMC_MIXED_FP16  3 /* as MIXED_BF16 with float16 cache storage       */
+
+/* what the couplings are, for the exact-energy outputs of tnmc_energy     */
+#define TNMC_COUPLING_GENERAL 0  /* any float32 couplings                    */
+#define TNMC_COUPLING_PMJ     1  /* every coupling is an integer (+-J): the   */
+                                 /* energy is also available as int32        */
+#define TNMC_COUPLING_GRID20  2  /* multiples of 2^-20 with |J| < 8: float64 */
+                                 /* energy sums are exact in any order       */
 
 /* largest bond dimension and lattice side the kernels are built for */
 /* launch orders of tnmc_run */
@@ -84,6 +94,7 @@ typedef struct tnmc_problem {
     const float   *J_v;     /* device     vertical couplings                  */
     const int64_t *off_h;   /* host [B] or NULL: element offset of instance i */
     const int64_t *off_v;   /*   in J_h / J_v; NULL = packed in batch order   */
+    int32_t coupling_kind;  /* TNMC_COUPLING_*, declares the exact-energy mode */
 } tnmc_problem;
 
 /* Per-instance Metropolis chain state (device memory, caller owned).
@@ -121,8 +132,15 @@ typedef struct tnmc_mlp {
 } tnmc_mlp;
 
 /* Bytes of workspace tnmc_build_env + tnmc_sample need for this problem at
- * this precision with up to max_samples samples per instance per call.
- * Returns TNMC_EINVAL on a bad problem.                                    */
+ * this precision with up to max_samples samples per instance per call:
+ * the cache (sections 3.2 and 3.4: every row of every instance stays in
+ * device memory), the build's scratch and the sampler's right environments.
+ * Returns 0 on a bad problem (tnmc_last_error says why).                   */
+size_t tnmc_workspace_bytes(const tnmc_problem *p, int32_t precision,
+                            int32_t max_samples);
+
+/* The same figure through a status code: TNMC_EINVAL on a bad problem,
+ * TNMC_ENOTSUP on a precision / size combination that is not built.       */
 int tnmc_workspace_size(const tnmc_problem *p, int32_t precision,
                         int32_t max_samples, size_t *bytes_out);
 
@@ -169,7 +187,9 @@ int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace,
              tnmc_env **env_out);
 
 /* Draw (or score) n_samples configurations per instance (section 3.3).
- *  seed, sample_offset  Philox key and first global sample index.
+ *  seed, sample_offset  Philox key and first global sample index; the
+ *                sample counter is 32 bits wide, so sample_offset +
+ *                n_samples must not exceed 2^32 (TNMC_EINVAL otherwise).
  *  forced_spins  device, NULL to sample; otherwise configurations in the
  *                packed layout to be scored (teacher forcing): the sampler
  *                evaluates their log q and logits instead of drawing.
@@ -186,13 +206,20 @@ int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed,
                 const tnmc_mlp *mlp, uint64_t *spins_out, double *logq_out,
                 float *logits_out, void *stream);
 
-/* Exact energies E(s) = -sum J s s over every bond once (Eq. (1)) of the
- * instances the env was built for (its couplings and sizes).
- *  spins   device, packed layout for n_samples per instance.
- *  E_out   device double [B][n_samples].  Exact for +-1 couplings and for
- *          couplings on the 2^-20 grid with |J| < 8.                       */
-int tnmc_energy(const tnmc_env *env, int32_t n_samples, const uint64_t *spins,
-                double *E_out, void *stream);
+/* Exact energies E(s) = -sum J s s over every bond once (Eq. (1)) of
+ * n_samples configurations per instance of the problem (its L, couplings
+ * and offsets; chi and beta are not read and may be NULL).
+ *  spins      device, packed layout for n_samples per instance.
+ *  E_out      device double [B][n_samples].  Exact for integer couplings
+ *             and for couplings on the 2^-20 grid with |J| < 8.
+ *  E_int_out  device int32 [B][n_samples] or NULL: the same energy summed
+ *             in integer arithmetic; only with coupling_kind
+ *             TNMC_COUPLING_PMJ (TNMC_EINVAL otherwise).  An instance with
+ *             a coupling that is not an integer gets INT32_MIN.
+ * Instances are processed in runs of equal L whose coupling offsets are
+ * evenly spaced (one launch per run).                                      */
+int tnmc_energy(const tnmc_problem *p, int32_t n_samples, const uint64_t *spins,
+                double *E_out, int32_t *E_int_out, void *stream);
 
 /* Metropolis independence step over each instance's proposals in index
  * order (Eq. (10)): with current state x and candidate k,
@@ -202,7 +229,8 @@ int tnmc_energy(const tnmc_env *env, int32_t n_samples, const uint64_t *spins,
  *  logq, E      device double [batch][n_samples]
  *  beta         device double [batch]
  *  chain        device tnmc_chain [batch], updated in place
- *  step_offset  global index of this call's first proposal (Philox counter)
+ *  step_offset  global index of this call's first proposal (Philox counter;
+ *               step_offset + n_samples must not exceed 2^32)
  *  accepted_out device uint8 [batch][n_samples] (1 = accepted)
  *  state_out    device int64 [batch][n_samples]: global index of the chain
  *               state after each proposal (NULL allowed).                  */
@@ -244,6 +272,14 @@ int tnmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t n_r
 int tnmc_mlp_forward(const float *params, int32_t n_rows, const float *feat,
                      int32_t bf16_weights, float *d_out, void *stream);
 
+/* Numeric health of an env's build: synchronises the stream, then returns
+ * TNMC_ENUMERIC if any instance has a row log-scale or ln Z that is not
+ * finite, or a truncation whose one-sided Jacobi stopped at its sweep limit
+ * (40 sweeps) before the columns were orthogonal to working precision;
+ * TNMC_OK otherwise.  tnmc_last_error() names the first such instance.
+ * The counts per instance are slots 8 and 9 of tnmc_env_stats.             */
+int tnmc_env_check(const tnmc_env *env, void *stream);
+
 /* Release an env (host memory only; the workspace stays the caller's).    */
 void tnmc_free_env(tnmc_env *env);
 
@@ -257,15 +293,18 @@ int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
                         uint32_t c2, uint32_t stream_id, int32_t n,
                         double *out, void *stream);
 
-/* Statistics of this env (device int64 [B][8], valid once the work has
+/* Statistics of this env (device int64 [B][16], valid once the work has
  * completed on its stream), per instance: the total number of Jacobi sweeps
  * over all truncations; wall-clock ticks (100 MHz device counter) spent in
  * the QR sweeps, in the SVD sweeps, and inside the Jacobi iterations of the
  * SVD sweeps; the ticks at which the instance's build started and ended;
  * the tick at which the first sample tile of the last tnmc_sample call
  * ended (the only tile when n_samples <= 256); the ticks spent in the
- * Householder factorisations (a part of the QR sweeps).  The build
- * processes instances in decreasing order of estimated cost (L-1) L chi^3.
+ * Householder factorisations (a part of the QR sweeps); the number of
+ * truncations whose Jacobi reached the sweep limit; the number of row
+ * log-scales (and ln Z) that are not finite; slots 10-15 are zero.  The
+ * build processes instances in decreasing order of estimated cost
+ * (L-1) L chi^3.
  * NULL for a NULL env.                                                    */
 const int64_t *tnmc_env_stats(const tnmc_env *env);
 

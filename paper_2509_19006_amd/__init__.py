@@ -14,7 +14,8 @@ from ctypes import POINTER, byref, c_double, c_int, c_int32, c_int64, c_size_t, 
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so")
 
-TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP = 0, -1, -2, -3, -4
+TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP, TNMC_ENUMERIC = 0, -1, -2, -3, -4, -5
+COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20 = 0, 1, 2
 FP64, FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
 SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
@@ -32,7 +33,7 @@ class TnmcError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("batch", c_int32), ("L", POINTER(c_int32)), ("chi", POINTER(c_int32)),
                 ("beta", POINTER(c_double)), ("J_h", c_void_p), ("J_v", c_void_p),
-                ("off_h", POINTER(c_int64)), ("off_v", POINTER(c_int64))]
+                ("off_h", POINTER(c_int64)), ("off_v", POINTER(c_int64)), ("coupling_kind", c_int32)]
 
 
 class _Mlp(ctypes.Structure):
@@ -44,7 +45,8 @@ MLP_LAYOUT = {"W1": (0, (64, 64)), "b1": (4096, (64,)), "W2": (4160, (64, 64)), 
               "W3": (8320, (64,)), "b3": (8384, (1,))}
 
 
-EXPORTS = ("tnmc_workspace_size", "tnmc_build_env", "tnmc_run", "tnmc_sample", "tnmc_energy", "tnmc_accept",
+EXPORTS = ("tnmc_workspace_bytes", "tnmc_workspace_size", "tnmc_build_env", "tnmc_run", "tnmc_sample",
+           "tnmc_energy", "tnmc_accept", "tnmc_env_check",
            "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats",
            "tnmc_mlp_features", "tnmc_mlp_scratch_floats", "tnmc_mlp_train_step", "tnmc_mlp_forward")
 
@@ -59,13 +61,16 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     P = POINTER
     lib.tnmc_workspace_size.argtypes = [P(_Problem), c_int32, c_int32, P(c_size_t)]
+    lib.tnmc_workspace_bytes.argtypes = [P(_Problem), c_int32, c_int32]
+    lib.tnmc_workspace_bytes.restype = c_size_t
+    lib.tnmc_env_check.argtypes = [c_void_p, c_void_p]
     lib.tnmc_build_env.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p), c_void_p]
     lib.tnmc_run.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_int32, c_uint64, c_uint64, c_void_p,
                              c_uint64, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                              c_int32, c_void_p, P(c_void_p)]
     lib.tnmc_sample.argtypes = [c_void_p, c_int32, c_uint64, c_uint64, c_void_p, P(_Mlp), c_void_p,
                                 c_void_p, c_void_p, c_void_p]
-    lib.tnmc_energy.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.tnmc_energy.argtypes = [P(_Problem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.tnmc_accept.argtypes = [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint64,
                                 c_uint64, c_void_p, c_void_p, c_void_p]
     lib.tnmc_free_env.argtypes = [c_void_p]
@@ -81,7 +86,7 @@ def load(path: str = LIB_PATH):
     lib.tnmc_mlp_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                         ctypes.c_float, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.tnmc_mlp_forward.argtypes = [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]
-    for name in ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy",
+    for name in ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy", "tnmc_env_check",
                  "tnmc_accept", "tnmc_philox_uniform", "tnmc_mlp_features", "tnmc_mlp_train_step",
                  "tnmc_mlp_forward"):
         getattr(lib, name).restype = c_int
@@ -109,9 +114,10 @@ class Problem:
 
     Either uniform: J_h (B, L, L-1), J_v (B, L-1, L) with scalar or per-instance
     chi/beta; or uneven: flat J_h / J_v with per-instance L and offsets.
+    coupling_kind is one of COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20.
     """
 
-    def __init__(self, J_h, J_v, L, chi, beta, off_h=None, off_v=None):
+    def __init__(self, J_h, J_v, L, chi, beta, off_h=None, off_v=None, coupling_kind=COUPLING_GENERAL):
         import numpy as np
         self.J_h, self.J_v = J_h, J_v
         B = len(L)
@@ -121,12 +127,13 @@ class Problem:
         self.off_h = None if off_h is None else np.ascontiguousarray(off_h, dtype=np.int64)
         self.off_v = None if off_v is None else np.ascontiguousarray(off_v, dtype=np.int64)
         self.batch = B
+        self.coupling_kind = int(coupling_kind)
         self._c = _Problem(
             B, self.L.ctypes.data_as(POINTER(c_int32)), self.chi.ctypes.data_as(POINTER(c_int32)),
             self.beta.ctypes.data_as(POINTER(c_double)),
             None if J_h is None else J_h.data_ptr(), None if J_v is None else J_v.data_ptr(),
             None if self.off_h is None else self.off_h.ctypes.data_as(POINTER(c_int64)),
-            None if self.off_v is None else self.off_v.ctypes.data_as(POINTER(c_int64)))
+            None if self.off_v is None else self.off_v.ctypes.data_as(POINTER(c_int64)), self.coupling_kind)
 
     @classmethod
     def uniform(cls, J_h, J_v, chi, beta):
@@ -138,6 +145,11 @@ class Problem:
 
     def spin_words_per_sample(self):
         return sum(int(L) * w for L, w in zip(self.L, self.words()))
+
+
+def tnmc_workspace_bytes(problem: Problem, precision: int, max_samples: int) -> int:
+    """Workspace bytes for the problem (0 on a bad problem; see tnmc_last_error)."""
+    return load().tnmc_workspace_bytes(byref(problem._c), precision, max_samples)
 
 
 def tnmc_workspace_size(problem: Problem, precision: int, max_samples: int) -> int:
@@ -195,9 +207,20 @@ def tnmc_sample(env: Env, n_samples: int, seed: int, spins_out, logq_out, sample
                            _ptr(logits_out), _stream(stream)))
 
 
-def tnmc_energy(env: Env, n_samples: int, spins, E_out, stream=None):
+def tnmc_energy(problem, n_samples: int, spins, E_out, E_int_out=None, stream=None):
+    """problem: a Problem, or an Env (its problem is used).  E_int_out (int32
+    (B, N), optional) needs coupling_kind COUPLING_PMJ."""
     lib = load()
-    _check(lib.tnmc_energy(env.handle, n_samples, _ptr(spins), _ptr(E_out), _stream(stream)))
+    if isinstance(problem, Env):
+        problem = problem.problem
+    _check(lib.tnmc_energy(byref(problem._c), n_samples, _ptr(spins), _ptr(E_out), _ptr(E_int_out),
+                           _stream(stream)))
+
+
+def tnmc_env_check(env: Env, stream=None):
+    """Synchronises the stream; raises TnmcError(TNMC_ENUMERIC) if a build
+    produced a non-finite log-scale or a Jacobi stopped at its sweep limit."""
+    _check(load().tnmc_env_check(env.handle, _stream(stream)))
 
 
 def tnmc_accept(logq, E, beta, chain, seed: int, step_offset: int, accepted_out, state_out=None,
@@ -216,15 +239,17 @@ def tnmc_philox_uniform(seed: int, c0, c1: int, c2: int, stream_id: int, out, st
                                    _stream(stream)))
 
 
-STATS_PER_INST = 8
+STATS_PER_INST = 16
+STAT_MAXSWEEP, STAT_NONFINITE = 8, 9
 
 
 def tnmc_env_stats(env: Env):
-    """Per-instance statistics as a host int64 array (B, 8): Jacobi sweeps;
+    """Per-instance statistics as a host int64 array (B, 16): Jacobi sweeps;
     100 MHz ticks spent in the QR sweeps, the SVD sweeps and the Jacobi
     loops; build start and end ticks; end tick of the first sampling tile
-    of the last tnmc_sample call; ticks in the Householder factorisations.
-    Synchronises the current stream."""
+    of the last tnmc_sample call; ticks in the Householder factorisations;
+    truncations whose Jacobi reached the sweep limit; non-finite row
+    log-scales.  Synchronises the current stream."""
     import numpy as np
     import torch
     addr = load().tnmc_env_stats(env.handle)

@@ -36,8 +36,8 @@ template <typename T, typename S>
 hipError_t launch_sample(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
                          uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *,
                          MlpArgs, int64_t *, hipStream_t);
-hipError_t launch_energy(const InstDesc *, int, int, const uint64_t *, const float *, const float *,
-                         double *, hipStream_t);
+hipError_t launch_energy_run(int, int, int, const uint64_t *, int64_t, const float *, int64_t, const float *,
+                             int64_t, double *, int32_t *, hipStream_t);
 hipError_t launch_accept(int, int, const double *, const double *, const double *, void *, uint64_t,
                          uint64_t, uint8_t *, int64_t *, hipStream_t);
 hipError_t launch_philox(uint64_t, const uint32_t *, uint32_t, uint32_t, uint32_t, int, double *,
@@ -112,8 +112,13 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
         if (p->off_h && p->off_h[i] < 0) return fail(TNMC_EINVAL, "negative J_h offset");
         if (p->off_v && p->off_v[i] < 0) return fail(TNMC_EINVAL, "negative J_v offset");
     }
+    if (p->coupling_kind < TNMC_COUPLING_GENERAL || p->coupling_kind > TNMC_COUPLING_GRID20)
+        return fail(TNMC_EINVAL, "unknown coupling_kind");
     return TNMC_OK;
 }
+
+// The Philox sample / proposal counter is one 32-bit word.
+bool counter_overflows(uint64_t offset, int32_t n) { return offset + (uint64_t)n > (uint64_t(1) << 32); }
 
 // Workspace layout: [desc table][build stats][per instance: log-scales,
 // cache, build scratch, previous-row ping-pong][sampler env tiles ...].
@@ -194,6 +199,11 @@ int check_lds(int precision, int chi_max, int L_max) {
 extern "C" {
 
 const char *tnmc_last_error(void) { return g_err.c_str(); }
+
+size_t tnmc_workspace_bytes(const tnmc_problem *p, int32_t precision, int32_t max_samples) {
+    size_t b = 0;
+    return tnmc_workspace_size(p, precision, max_samples, &b) == TNMC_OK ? b : 0;
+}
 
 int tnmc_workspace_size(const tnmc_problem *p, int32_t precision, int32_t max_samples, size_t *bytes_out) {
     int rc = validate(p, precision, false);
@@ -286,6 +296,8 @@ int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace, size_t w
              double *E_out, uint8_t *accepted_out, int64_t *state_out, double *logz_out, int32_t schedule,
              void *stream, tnmc_env **env_out) {
     if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
+    if (counter_overflows(sample_offset, n_samples) || counter_overflows(step_offset, n_samples))
+        return fail(TNMC_EINVAL, "sample_offset / step_offset + n_samples exceeds the 32-bit Philox counter");
     if (!spins_out || !logq_out || !E_out || !accepted_out || !chain)
         return fail(TNMC_EINVAL, "spins_out, logq_out, E_out, accepted_out and chain must be non-NULL");
     Plan pl;
@@ -318,6 +330,8 @@ int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed, uint64_t sample
                 double *logq_out, float *logits_out, void *stream) {
     if (!env) return fail(TNMC_EINVAL, "env is NULL");
     if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
+    if (counter_overflows(sample_offset, n_samples))
+        return fail(TNMC_EINVAL, "sample_offset + n_samples exceeds the 32-bit Philox sample counter");
     if (!spins_out || !logq_out) return fail(TNMC_EINVAL, "spins_out and logq_out must be non-NULL");
     const int tiles = (n_samples + tnmc::kSampleTile - 1) / tnmc::kSampleTile;
     if (tiles > env->max_tiles)
@@ -344,14 +358,69 @@ int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed, uint64_t sample
     return TNMC_OK;
 }
 
-int tnmc_energy(const tnmc_env *env, int32_t n_samples, const uint64_t *spins, double *E_out, void *stream) {
-    if (!env) return fail(TNMC_EINVAL, "env is NULL");
+int tnmc_energy(const tnmc_problem *p, int32_t n_samples, const uint64_t *spins, double *E_out,
+                int32_t *E_int_out, void *stream) {
+    if (!p) return fail(TNMC_EINVAL, "problem is NULL");
+    if (p->batch < 1 || !p->L) return fail(TNMC_EINVAL, "batch must be >= 1 with a host L array");
+    if (!p->J_h || !p->J_v) return fail(TNMC_EINVAL, "J_h and J_v must be non-NULL device arrays");
     if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
     if (!spins || !E_out) return fail(TNMC_EINVAL, "spins and E_out must be non-NULL");
-    const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + env->desc_off);
-    hipError_t e = tnmc::launch_energy(dd, env->batch, n_samples, spins, env->J_h, env->J_v, E_out,
-                                       static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    if (p->coupling_kind < TNMC_COUPLING_GENERAL || p->coupling_kind > TNMC_COUPLING_GRID20)
+        return fail(TNMC_EINVAL, "unknown coupling_kind");
+    if (E_int_out && p->coupling_kind != TNMC_COUPLING_PMJ)
+        return fail(TNMC_EINVAL, "E_int_out needs coupling_kind TNMC_COUPLING_PMJ");
+    const int B = p->batch;
+    std::vector<int64_t> oh(B), ov(B), wpre(B);
+    int64_t ah = 0, av = 0, wp = 0;
+    for (int i = 0; i < B; ++i) {
+        const int L = p->L[i];
+        if (L < 2 || L > TNMC_L_MAX)
+            return fail(TNMC_EINVAL, "instance " + std::to_string(i) + ": L must be in [2, " + std::to_string(TNMC_L_MAX) + "]");
+        oh[i] = p->off_h ? p->off_h[i] : ah;
+        ov[i] = p->off_v ? p->off_v[i] : av;
+        if (oh[i] < 0 || ov[i] < 0) return fail(TNMC_EINVAL, "negative coupling offset");
+        ah += (int64_t)L * (L - 1);
+        av += (int64_t)(L - 1) * L;
+        wpre[i] = wp;
+        wp += (int64_t)L * ((L + 63) / 64);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // runs of equal L with evenly spaced coupling offsets: one launch each
+    for (int i0 = 0; i0 < B;) {
+        const int L = p->L[i0];
+        int i1 = i0 + 1;
+        if (i1 < B && p->L[i1] == L) {
+            const int64_t dh = oh[i1] - oh[i0], dv = ov[i1] - ov[i0];
+            while (i1 < B && p->L[i1] == L && oh[i1] - oh[i1 - 1] == dh && ov[i1] - ov[i1 - 1] == dv) ++i1;
+        }
+        const int64_t sh = i1 - i0 > 1 ? oh[i0 + 1] - oh[i0] : 0, sv = i1 - i0 > 1 ? ov[i0 + 1] - ov[i0] : 0;
+        const int64_t iw = (int64_t)n_samples * L * ((L + 63) / 64);
+        hipError_t e = tnmc::launch_energy_run(L, i1 - i0, n_samples, spins + (size_t)n_samples * wpre[i0], iw,
+                                               p->J_h + oh[i0], sh, p->J_v + ov[i0], sv,
+                                               E_out + (size_t)i0 * n_samples,
+                                               E_int_out ? E_int_out + (size_t)i0 * n_samples : nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "energy launch");
+        i0 = i1;
+    }
+    return TNMC_OK;
+}
+
+int tnmc_env_check(const tnmc_env *env, void *stream) {
+    if (!env) return fail(TNMC_EINVAL, "env is NULL");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "stream synchronisation");
+    std::vector<int64_t> st((size_t)tnmc::STATS_PER_INST * env->batch);
+    e = hipMemcpy(st.data(), env->ws + env->sweeps_off, st.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "statistics read");
+    for (int i = 0; i < env->batch; ++i) {
+        const int64_t *s = st.data() + (size_t)tnmc::STATS_PER_INST * i;
+        if (s[tnmc::STAT_NONFINITE])
+            return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_NONFINITE]) +
+                                           " row log-scale(s) or ln Z not finite");
+        if (s[tnmc::STAT_MAXSWEEP])
+            return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_MAXSWEEP]) +
+                                           " truncation(s) reached the Jacobi sweep limit");
+    }
     return TNMC_OK;
 }
 
@@ -359,6 +428,8 @@ int tnmc_accept(int32_t batch, int32_t n_samples, const double *logq, const doub
                 tnmc_chain *chain, uint64_t seed, uint64_t step_offset, uint8_t *accepted_out,
                 int64_t *state_out, void *stream) {
     if (batch < 1 || n_samples < 1) return fail(TNMC_EINVAL, "batch and n_samples must be >= 1");
+    if (counter_overflows(step_offset, n_samples))
+        return fail(TNMC_EINVAL, "step_offset + n_samples exceeds the 32-bit Philox proposal counter");
     if (!logq || !E || !beta || !chain || !accepted_out) return fail(TNMC_EINVAL, "NULL array argument");
     hipError_t e = tnmc::launch_accept(batch, n_samples, logq, E, beta, chain, seed, step_offset, accepted_out,
                                        state_out, static_cast<hipStream_t>(stream));

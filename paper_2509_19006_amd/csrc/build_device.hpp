@@ -1013,7 +1013,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     // the current row's couplings (vertical, then horizontal)
     float *jrow = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(mq + 2 * (L + 1)) + 3) & ~(uintptr_t)3);
 
-    int total_sweeps = 0;
+    int total_sweeps = 0, maxsweep_hits = 0;
     long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0, cyc_hh = 0;   // wall-clock ticks per phase
 
     // write one parity-basis site (from a generator) to the ping-pong buffer
@@ -1277,6 +1277,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
+                maxsweep_hits += (iflag[0] >= MAX_SWEEPS) + (iflag[1] >= MAX_SWEEPS);
                 cyc_jac += wall_clock64() - t0;
             }
             // singular values of both blocks (padding columns and empty
@@ -1389,10 +1390,14 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     }
     if (tid == 0) {
         double lz = logz_tail;
-        for (int r = 0; r < L; ++r) lz += lsc[r];
+        int nonfinite = 0;
+        for (int r = 0; r < L; ++r) { lz += lsc[r]; nonfinite += !isfinite(lsc[r]); }
+        nonfinite += !isfinite(lz);
         if (logz_out) logz_out[inst] = lz;
         if (stats_out) {
             int64_t *so = stats_out + STATS_PER_INST * inst;
+            so[STAT_MAXSWEEP] = maxsweep_hits;
+            so[STAT_NONFINITE] = nonfinite;
             so[0] = total_sweeps;
             so[1] = cyc_qr;
             so[2] = cyc_svd;

@@ -26,8 +26,11 @@ static_assert(sizeof(InstDesc) == 96, "InstDesc layout");
 // Per-instance statistics record (int64): Jacobi sweeps, wall-clock ticks
 // in QR sweeps / SVD sweeps / Jacobi loops, build start and end ticks, end
 // tick of the instance's last sampling tile, ticks in the Householder
-// factorisations (part of the QR sweeps).
-constexpr int STATS_PER_INST = 8;
+// factorisations (part of the QR sweeps); then the numeric-failure counts:
+// truncations whose Jacobi stopped at the sweep limit without converging,
+// and rows whose log-scale (or the final ln Z) is not finite.
+constexpr int STATS_PER_INST = 16;
+constexpr int STAT_MAXSWEEP = 8, STAT_NONFINITE = 9;
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) -----------------------------------
 struct U4 { uint32_t x, y, z, w; };

@@ -8,15 +8,29 @@
 
 namespace tnmc {
 
-// One wave per (sample, instance).
+// Energies of a run of instances that share the side L (one wave per
+// (sample, instance of the run)); instance j of the run has its couplings
+// at Jh + j*stride_h, Jv + j*stride_v and its configurations at
+// spins + j*inst_words.  With E_int non-NULL the energy is also summed in
+// int32 from the couplings taken as integers; an instance with a coupling
+// that is not an integer gets INT32_MIN there.
 __global__ void __launch_bounds__(64)
-k_energy(const InstDesc *__restrict__ desc, int n_samples, const uint64_t *__restrict__ spins,
-         const float *__restrict__ Jh_all, const float *__restrict__ Jv_all, double *__restrict__ E_out) {
-    const int inst = blockIdx.y, n = blockIdx.x, lane = threadIdx.x;
-    const InstDesc d = desc[inst];
-    const uint64_t *s = spins + (size_t)n_samples * d.word_prefix + (size_t)n * d.L * d.W;
-    const double e = energy_wave(d, s, Jh_all, Jv_all, lane);
-    if (lane == 0) E_out[(size_t)inst * n_samples + n] = e;
+k_energy_run(int L, int n_samples, const uint64_t *__restrict__ spins, int64_t inst_words,
+             const float *__restrict__ Jh, int64_t stride_h, const float *__restrict__ Jv, int64_t stride_v,
+             double *__restrict__ E_out, int32_t *__restrict__ E_int) {
+    const int j = blockIdx.y, n = blockIdx.x, lane = threadIdx.x;
+    InstDesc d{};
+    d.L = L;
+    d.W = (L + 63) / 64;
+    d.off_h = (int64_t)j * stride_h;
+    d.off_v = (int64_t)j * stride_v;
+    const uint64_t *s = spins + (size_t)j * inst_words + (size_t)n * L * d.W;
+    const double e = energy_wave(d, s, Jh, Jv, lane);
+    if (E_int) {
+        const int64_t ei = energy_wave_int(d, s, Jh, Jv, lane);
+        if (lane == 0) E_int[(size_t)j * n_samples + n] = ei == INT64_MIN ? INT32_MIN : (int32_t)ei;
+    }
+    if (lane == 0) E_out[(size_t)j * n_samples + n] = e;
 }
 
 // One thread per instance walks its proposals in order.
@@ -35,9 +49,11 @@ __global__ void k_philox(uint64_t seed, const uint32_t *__restrict__ c0, uint32_
     if (k < n) out[k] = philox_unit(seed, c0[k], c1, c2, c3);
 }
 
-hipError_t launch_energy(const InstDesc *desc, int B, int n_samples, const uint64_t *spins,
-                         const float *Jh, const float *Jv, double *E, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy, dim3(n_samples, B), dim3(64), 0, st, desc, n_samples, spins, Jh, Jv, E);
+hipError_t launch_energy_run(int L, int n_inst, int n_samples, const uint64_t *spins, int64_t inst_words,
+                             const float *Jh, int64_t stride_h, const float *Jv, int64_t stride_v, double *E,
+                             int32_t *E_int, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_run, dim3(n_samples, n_inst), dim3(64), 0, st, L, n_samples, spins, inst_words, Jh,
+                       stride_h, Jv, stride_v, E, E_int);
     return hipGetLastError();
 }
 

@@ -39,6 +39,42 @@ __device__ inline double energy_wave(const InstDesc &d, const uint64_t *s, const
     return e;
 }
 
+// The same sum in integer arithmetic, for couplings that are integers
+// (+-J): every lane returns the energy, or INT64_MIN when some coupling of
+// the instance is not an integer of magnitude below 2^20 (|E| then stays
+// below 2^42, far inside int64; the int32 result is exact for L <= 1024,
+// where |E| <= 2 L (L-1) max|J|, with +-1 couplings).
+__device__ inline int64_t energy_wave_int(const InstDesc &d, const uint64_t *s, const float *Jh_all,
+                                          const float *Jv_all, int lane) {
+    const int L = d.L, W = d.W;
+    const float *jh = Jh_all + d.off_h, *jv = Jv_all + d.off_v;
+    int64_t e = 0;
+    int bad = 0;
+    for (int r = lane; r < L; r += 64) {
+        const uint64_t *row = s + (size_t)r * W, *nxt = s + (size_t)(r + 1) * W;
+        for (int c = 0; c < L; ++c) {
+            const int sc = ((row[c >> 6] >> (c & 63)) & 1) ? 1 : -1;
+            if (c + 1 < L) {
+                const float j = jh[(size_t)r * (L - 1) + c];
+                bad |= !(j == rintf(j) && fabsf(j) < 1048576.0f);
+                const int sr = ((row[(c + 1) >> 6] >> ((c + 1) & 63)) & 1) ? 1 : -1;
+                e -= (int64_t)j * (sc * sr);
+            }
+            if (r + 1 < L) {
+                const float j = jv[(size_t)r * L + c];
+                bad |= !(j == rintf(j) && fabsf(j) < 1048576.0f);
+                const int sd = ((nxt[c >> 6] >> (c & 63)) & 1) ? 1 : -1;
+                e -= (int64_t)j * (sc * sd);
+            }
+        }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+        e += __shfl_xor(e, m, 64);
+        bad |= __shfl_xor(bad, m, 64);
+    }
+    return bad ? INT64_MIN : e;
+}
+
 // Instance i's chain walks its n proposals (log q, E) in index order: the
 // first ever proposal initialises it; then with current state x and
 // candidate k, delta = (lq_x - lq_k) + beta (E_x - E_k), each operation

@@ -76,7 +76,8 @@ def test_entry_points_reject_bad_arguments_before_device_work(lib):
     assert lib.tnmc_build_env(ctypes.byref(p._c), T.FP32, ctypes.c_void_p(256), 1 << 30, None,
                               ctypes.byref(env), None) == T.TNMC_EINVAL
     assert lib.tnmc_sample(None, 4, 0, 0, None, None, None, None, None, None) == T.TNMC_EINVAL
-    assert lib.tnmc_energy(None, 4, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_energy(None, 4, None, None, None, None) == T.TNMC_EINVAL
+    assert lib.tnmc_env_check(None, None) == T.TNMC_EINVAL
     assert lib.tnmc_accept(0, 4, None, None, None, None, 0, 0, None, None, None) == T.TNMC_EINVAL
     assert lib.tnmc_accept(2, 4, None, None, None, None, 0, 0, None, None, None) == T.TNMC_EINVAL
     assert lib.tnmc_philox_uniform(0, None, 0, 0, 0, 4, None, None) == T.TNMC_EINVAL
@@ -97,3 +98,54 @@ def test_chain_state_decoding():
     i[1, 2], i[1, 3], i[1, 4], i[1, 5] = 41, 7, 40, 1
     st = T.chain_state(raw)
     assert st[1] == dict(cur_logq=-3.5, cur_E=12.0, cur_index=41, n_acc=7, n_trials=40, initialised=1)
+
+
+def test_workspace_bytes_matches_status_form(lib):
+    p = _problem((16, 33), (8, 8), (1.0, 0.5))
+    assert T.tnmc_workspace_bytes(p, T.FP32, 300) == T.tnmc_workspace_size(p, T.FP32, 300) > 0
+    # a bad problem gives 0 and an error text
+    assert T.tnmc_workspace_bytes(_problem((1,), (4,), (1.0,)), T.FP32, 8) == 0
+    assert b"L must be" in lib.tnmc_last_error()
+    assert T.tnmc_workspace_bytes(p, T.FP32, 0) == 0
+
+
+def test_coupling_kind_is_validated(lib):
+    p = T.Problem(None, None, [8], [8], [1.0], coupling_kind=7)
+    with pytest.raises(T.TnmcError) as e:
+        T.tnmc_workspace_size(p, T.FP32, 8)
+    assert e.value.code == T.TNMC_EINVAL
+
+
+def _fake_problem(L, kind):
+    """A problem whose device pointers are never dereferenced (the calls
+    below fail validation before any device work)."""
+    p = T.Problem(None, None, list(L), [8] * len(L), [1.0] * len(L), coupling_kind=kind)
+    p._c.J_h = ctypes.c_void_p(256)
+    p._c.J_v = ctypes.c_void_p(512)
+    return p
+
+
+def test_energy_validation(lib):
+    fake = ctypes.c_void_p(1024)
+    # the int32 output needs +-J couplings
+    for kind in (T.COUPLING_GENERAL, T.COUPLING_GRID20):
+        p = _fake_problem((8, 8), kind)
+        assert lib.tnmc_energy(ctypes.byref(p._c), 4, fake, fake, fake, None) == T.TNMC_EINVAL
+        assert b"COUPLING_PMJ" in lib.tnmc_last_error()
+    p = _fake_problem((8, 1), T.COUPLING_PMJ)
+    assert lib.tnmc_energy(ctypes.byref(p._c), 4, fake, fake, fake, None) == T.TNMC_EINVAL
+    p = _fake_problem((8,), T.COUPLING_PMJ)
+    assert lib.tnmc_energy(ctypes.byref(p._c), 0, fake, fake, fake, None) == T.TNMC_EINVAL
+    assert lib.tnmc_energy(ctypes.byref(p._c), 4, None, fake, None, None) == T.TNMC_EINVAL
+
+
+def test_philox_counter_overflow_is_rejected(lib):
+    fake = ctypes.c_void_p(1024)
+    # 2^32 - 4 + 8 proposals would wrap the 32-bit proposal counter
+    rc = lib.tnmc_accept(2, 8, fake, fake, fake, fake, 0, (1 << 32) - 4, fake, None, None)
+    assert rc == T.TNMC_EINVAL and b"Philox" in lib.tnmc_last_error()
+    env = ctypes.c_void_p(0)
+    p = _fake_problem((8,), T.COUPLING_PMJ)
+    rc = lib.tnmc_run(ctypes.byref(p._c), T.FP32, fake, 1 << 30, 8, 0, (1 << 32) - 1, fake, 0, 0, fake, fake,
+                      fake, fake, None, None, 0, None, ctypes.byref(env))
+    assert rc == T.TNMC_EINVAL and b"Philox" in lib.tnmc_last_error()
