@@ -241,17 +241,23 @@ def run_uneven(args):
     T.load()
     spec = c4_spec()
     N = 32
-    log(f"uneven batch: {len(spec)} instances, {N} samples each; tuning the schedule on a 1/4-scale replica "
-        f"(objective {args.objective})")
-    name, mode, order, table = autotune.tune(lambda L, fam, i: workloads.instance(L, fam, 40, i), spec, T.FP32,
-                                             N, objective=args.objective, scale=4)
-    for k, (v, r) in table.items():
-        c = r["completion_s"]
-        log(f"  {k}: {args.objective} {v:.3f} s, wall {r['wall_s']:.3f} s, p50 {np.percentile(c, 50):.3f} s, "
-            f"p99 {np.percentile(c, 99):.3f} s")
-    log(f"chosen: {name}; full batch ...")
     Js = [workloads.instance(L, fam, 4, i) for i, (L, fam, _, _) in enumerate(spec)]
-    res = autotune.run_schedule(Js, [c for _, _, c, _ in spec], [b for _, _, _, b in spec], T.FP32, N, mode, order)
+    chis = [c for _, _, c, _ in spec]
+    betas = [b for _, _, _, b in spec]
+    log(f"uneven batch: {len(spec)} instances, {N} samples each; the library's tuner times the candidate "
+        f"schedules on a 1/4-scale sub-lattice replica (objective {args.objective})")
+    cache = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gpurun_out", "tnmc_tuning.txt")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    tune = autotune.tune(Js, chis, betas, T.FP32, N, objective=args.objective, scale=4, cache_path=cache)
+    cands = ["longest-first", "shortest-first", "as given", "split by bond class"]
+    for k, v in zip(cands, tune["candidates_s"]):
+        log(f"  {k}: {args.objective} {v:.3f} s (replica)")
+    name = cands[3] if tune["split"] else cands[tune["schedule"]]
+    log(f"chosen: {name}{' (from the tuning cache)' if tune['from_cache'] else ''}; full batch ...")
+    res = autotune.run_schedule(Js, chis, betas, T.FP32, N, tune["split"], tune["schedule"], decode_steps=4)
+    dec = res["decode"]
+    log(f"  then 4 decode steps per instance from one captured graph: {dec['wall_s']:.2f} s, acceptance "
+        f"{dec['accepted'] / max(1, dec['trials']):.4f}")
     c = res["completion_s"]
     by_class = {}
     for (L, _, chi, _), t in zip(spec, c):
@@ -269,10 +275,10 @@ def run_uneven(args):
         "completion_p50_s": float(np.percentile(c, 50)), "completion_p99_s": float(np.percentile(c, 99)),
         "completion_max_s": float(c.max()),
         "completion_median_by_class_s": {k: float(np.median(v)) for k, v in sorted(by_class.items())},
-        "tuner_replica": {k: {"objective": v, "wall_s": r["wall_s"],
-                              "p50_s": float(np.percentile(r["completion_s"], 50)),
-                              "p99_s": float(np.percentile(r["completion_s"], 99))}
-                          for k, (v, r) in table.items()},
+        "tuner_replica_objective_s": dict(zip(cands, tune["candidates_s"])),
+        "graph_decode": {"steps_per_instance": dec["steps"], "samples_per_step": N, "wall_s": dec["wall_s"],
+                         "accepted": dec["accepted"], "trials": dec["trials"],
+                         "accepted_per_s_cache_reused": dec["accepted"] / dec["wall_s"]},
     }
     print(json.dumps(line), flush=True)
 
@@ -363,21 +369,115 @@ def run_learned(args):
     print(json.dumps(line), flush=True)
 
 
+# The paper's single-GPU run (+-J EA, 1024 x 1024, beta 1, chi 8, 10^3
+# disorders x 10^3 samples): 3.3 h at acceptance ~0.37, i.e. 10^6 proposals in
+# 11 880 s, 0.37 * 10^6 / 11 880 = 31.1 accepted samples/s, on a GPU whose
+# model the paper does not state.
+PAPER_SECONDS = 3.3 * 3600
+PAPER_ACCEPTED_PER_S = 0.37 * 1e6 / PAPER_SECONDS
+
+
+def run_paper(args):
+    """The paper's run: +-J EA lattices of 1024 x 1024 at beta 1, chi 8,
+    every disorder's couplings resident in HBM, the disorders processed in
+    chunks whose caches fit the memory budget (float32 path)."""
+    import numpy as np
+    import torch
+    import paper_2509_19006_amd as T
+    from paper_2509_19006_amd import chunked
+    import workloads
+    T.load()
+    L, chi, B, N, beta = args.L, args.chi, args.disorders, args.samples, args.beta
+    log(f"paper workload: {B} +-J disorders of {L}x{L}, beta {beta}, chi {chi}, {N} samples each")
+    t0 = time.time()
+    jh = torch.empty((B, L, L - 1), dtype=torch.float32, device="cuda")
+    jv = torch.empty((B, L - 1, L), dtype=torch.float32, device="cuda")
+    for i in range(B):
+        a, b = workloads.instance(L, "pmj", 8, i)
+        jh[i].copy_(torch.from_numpy(a))
+        jv[i].copy_(torch.from_numpy(b))
+    torch.cuda.synchronize()
+    log(f"  couplings generated and uploaded in {time.time() - t0:.0f} s (not timed)")
+    res = chunked.run(jh, jv, L, chi, beta, T.FP32, N, 0x5A5A0008, budget_bytes=args.budget_gb * 1e9,
+                      coupling_kind=T.COUPLING_PMJ, log=log)
+    acc, tr = int(res["n_acc"].sum()), int(res["n_trials"].sum())
+    per_inst = res["n_acc"] / np.maximum(1, res["n_trials"])
+    value = acc / res["wall_s"]
+    line = {
+        "metric": "accepted samples/s + acceptance rate, the paper's 1024x1024 +-J run",
+        "value": value, "unit": "accepted samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": res["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": value / PAPER_ACCEPTED_PER_S, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"paper run: {B} +-J EA disorders of {L}x{L}, beta {beta}, chi {chi}, {N} samples "
+                               f"each, float32, disorders in chunks of {res['chunks'][0][1]}"},
+        "acceptance": acc / max(1, tr),
+        "acceptance_per_disorder_mean_sd": [float(per_inst.mean()), float(per_inst.std(ddof=1)) if B > 1 else 0.0],
+        "wall_s": res["wall_s"], "build_s": res["build_s"], "sample_s": res["sample_s"],
+        "energy_s": res["energy_s"], "accept_s": res["accept_s"],
+        "energy_per_spin_chain_mean": float(res["e_mean"].mean() / (L * L)),
+        "proposals_per_s": B * N / res["wall_s"],
+        "paper": {"seconds": PAPER_SECONDS, "acceptance": 0.37, "accepted_per_s": PAPER_ACCEPTED_PER_S,
+                  "hardware": "one GPU, model not stated", "speedup_wall": PAPER_SECONDS * (B * N / 1e6) / res["wall_s"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_sweep(args):
+    """Acceptance against L, chi and beta on +-J EA lattices (the paper's
+    acceptance figure): for every (L, chi, beta) 16 disorders x 64 samples,
+    float32, run through the chunked driver."""
+    import numpy as np
+    import torch
+    import paper_2509_19006_amd as T
+    from paper_2509_19006_amd import chunked
+    import workloads
+    T.load()
+    Ls = [8, 16, 32, 64, 128, 256, 512, 1024]
+    chis = [2, 4, 8, 16, 32]
+    betas = [0.66, 1.0, 1.5]
+    D, N = 16, 64
+    table = []
+    t0 = time.time()
+    for L in Ls:
+        jh = torch.as_tensor(np.stack([workloads.instance(L, "pmj", 9, i)[0] for i in range(D)])).cuda()
+        jv = torch.as_tensor(np.stack([workloads.instance(L, "pmj", 9, i)[1] for i in range(D)])).cuda()
+        for chi in chis:
+            if L >= 1024 and chi > 16:
+                continue
+            for beta in betas:
+                res = chunked.run(jh, jv, L, chi, beta, T.FP32, N, 0x5A5A0009, coupling_kind=T.COUPLING_PMJ)
+                a = res["n_acc"] / np.maximum(1, res["n_trials"])
+                table.append({"L": L, "chi": chi, "beta": beta, "acceptance": float(a.mean()),
+                              "sd_over_disorders": float(a.std(ddof=1)), "wall_s": res["wall_s"]})
+                log(f"  L {L:5d} chi {chi:3d} beta {beta:.2f}: acceptance {a.mean():.4f} "
+                    f"(sd {a.std(ddof=1):.3f}), {res['wall_s']:.1f} s")
+    line = {"metric": "acceptance rate against L, chi and beta (+-J EA, 16 disorders x 64 samples)",
+            "value": None, "unit": "acceptance", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": (time.time() - t0) * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "acceptance sweep: L in 8..1024, chi in 2..32, beta in {0.66, 1, 1.5}"},
+            "table": table}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--L", type=int, default=256)
-    ap.add_argument("--chi", type=int, default=32)
-    ap.add_argument("--disorders", type=int, default=256)
-    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--L", type=int, default=None, help="lattice side (headline 256, paper 1024)")
+    ap.add_argument("--chi", type=int, default=None, help="bond dimension (headline 32, paper 8)")
+    ap.add_argument("--disorders", type=int, default=None, help="disorders (headline 256, paper 1000)")
+    ap.add_argument("--samples", type=int, default=None, help="samples per disorder (headline 256, paper 1000)")
     ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--mixed", choices=["bf16", "fp16"], default="fp16")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the stored-cache comparison form")
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="paper / sweep: device memory for one chunk of disorders")
+    ap.add_argument("--forms", default="fp32,bf16x3,fp16",
+                    help="precision forms of the headline workload, comma separated (the first is fp32): "
+                         "fp32, bf16x3, fp16, bf16")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "uneven", "learned"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "uneven", "learned", "paper", "sweep"], default="headline",
                     help="headline: the 256x256 batch (default); uneven: the 512-instance mix in one "
                          "persistent launch with an autotuned schedule; learned: the learned correction "
                          "(use with --L 1024 --disorders 64 --samples 16)")
@@ -390,6 +490,10 @@ def main():
                     help="only run a plain device-to-device copy of this many GiB three times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    dflt = {"paper": (1024, 8, 1000, 1000), "learned": (1024, 16, 64, 16)}.get(args.workload, (256, 32, 256, 256))
+    for k, v in zip(("L", "chi", "disorders", "samples"), dflt):
+        if getattr(args, k) is None:
+            setattr(args, k, v)
     if args.cpu_baseline_child:
         cpu_baseline_child(args.L, args.chi, args.beta, args.samples)
         return
@@ -419,6 +523,12 @@ def main():
     if args.workload == "learned":
         run_learned(args)
         return
+    if args.workload == "paper":
+        run_paper(args)
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
+        return
     import paper_2509_19006_amd as T
     import workloads
     T.load()
@@ -430,13 +540,13 @@ def main():
     jv = torch.as_tensor(jv_np).cuda()
     seed = 0x5A5A0003
 
-    mixed_prec = T.MIXED_BF16 if args.mixed == "bf16" else T.MIXED_FP16
-    log("plain float32 form:")
-    plain = run_form(T, torch, T.FP32, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
-    mixed = None
-    if not args.no_mixed:
-        log(f"stored-cache form ({args.mixed} cache, float32 build):")
-        mixed = run_form(T, torch, mixed_prec, jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+    forms = {}
+    names = {"fp32": "plain float32", "bf16x3": "mixed: bf16 matrix-core sampler with split operands",
+             "fp16": "float16-stored cache", "bf16": "bfloat16-stored cache"}
+    for f in args.forms.split(","):
+        log(f"{names[f]} form:")
+        forms[f] = run_form(T, torch, T.PRECISIONS[f], jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+    plain = forms["fp32"]
 
     # the dominant kernel: the cache build (float32 vector ALU, latency bound)
     S = plain["jacobi_sweeps_per_site"]
@@ -458,21 +568,22 @@ def main():
     # the sampler, by form: algorithmic flops and bytes against the roof its
     # intensity selects
     roof_sample = {}
-    for name, f, eb, peak, pname in (("plain_fp32", plain, 4, PEAK["fp32"], "fp32 vector/MFMA"),
-                                     (f"mixed_{args.mixed}", mixed, 2, PEAK["mfma16"], "bf16/fp16 MFMA dense")):
-        if f is None:
-            continue
+    kinds = {"fp32": (4, PEAK["fp32"], "float32 MFMA"), "bf16x3": (4, PEAK["mfma16"], "bf16 MFMA dense"),
+             "fp16": (2, PEAK["mfma16"], "fp16 MFMA dense"), "bf16": (2, PEAK["mfma16"], "bf16 MFMA dense")}
+    for name, f in forms.items():
+        eb, peak, pname = kinds[name]
         fl, by = sample_flops(L, chi, B, N), sample_bytes(L, chi, B, N, eb)
         t = f["sample_ms"] * 1e-3
         ridge = peak / PEAK["hbm"]
         bound_hbm = fl / by < ridge
         roof_sample[name] = {
-            "kernel": "k_sample", "bound": "hbm" if bound_hbm else "mfma",
+            "kernel": "k_sample_mfma", "bound": "hbm" if bound_hbm else "mfma",
             "achieved": (by / t / 1e9) if bound_hbm else (fl / t / 1e12),
             "peak": (PEAK["hbm"] / 1e9) if bound_hbm else (peak / 1e12),
             "unit": "GB/s" if bound_hbm else "TFLOP/s",
             "frac": (by / t / PEAK["hbm"]) if bound_hbm else (fl / t / peak),
             "flops_per_launch": fl, "algorithmic_bytes": by, "intensity_flop_per_byte": fl / by,
+            "hbm_frac_of_algorithmic_bytes": by / t / PEAK["hbm"],
             "peak_kind": pname, "traffic": None}
 
     cpu = finish_cpu_baseline(cpu_proc) if cpu_proc is not None else None
@@ -484,10 +595,10 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"TNMC on {L}x{L} open +-J EA lattices, beta={beta}, chi={chi}, {B} disorders x "
                                 f"{N} samples: float32 build and sampler, float64 log-weights and accept, int32 "
-                                f"energies; beside it the {args.mixed}-stored-cache form on the same inputs"),
+                                f"energies; beside it the other precision forms on the same inputs"),
                    "L": L, "chi": chi, "disorders": B, "samples": N, "beta": beta, "form": "plain-fp32"},
         "acceptance": plain["acceptance"],
-        "plain_fp32": plain, f"mixed_{args.mixed}": mixed,
+        "forms": forms,
         "roofline": roof, "roofline_sample": roof_sample, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -60,13 +60,25 @@ extern "C" {
                               stopped at its sweep limit (tnmc_env_check)   */
 
 /* ---- precision of the boundary-MPS build and of the sampler ----------- */
-#define TNMC_FP64        0 /* everything in float64                          */
-#define TNMC_FP32        1 /* contractions, QR, SVD and cache in float32;    */
-                           /* log-weights, log q and accept in float64       */
-#define TNMC_MIXED_BF16  2 /* build in float32, cache stored in bfloat16;   */
-                           /* the sampler widens each stored entry to float32 */
-                           /* and contracts in float32                       */
-#define TNMC_MIXED_FP16  3 /* as MIXED_BF16 with float16 cache storage       */
+/* Every form keeps log-scales, ln Z, log q, p(+1), the Metropolis log-ratio
+ * and the accept decision in float64.  In the float forms the sampler's two
+ * contractions per site run on the matrix cores for chi <= 32 (the sample
+ * vectors are float32 and enter 16-bit products as hi + lo pairs) and on the
+ * vector unit in float32 for chi > 32.                                    */
+#define TNMC_FP64        0 /* build, cache and sampler in float64 (vector    */
+                           /* unit)                                          */
+#define TNMC_FP32        1 /* build and cache in float32; sampler products   */
+                           /* on float32 matrix cores                        */
+#define TNMC_MIXED_BF16  2 /* float32 build, cache stored in bfloat16; the   */
+                           /* sampler's products on bf16 matrix cores with   */
+                           /* float32 accumulation (the stored entries enter */
+                           /* exactly)                                       */
+#define TNMC_MIXED_FP16  3 /* as MIXED_BF16 with a float16 cache and float16 */
+                           /* matrix cores                                   */
+#define TNMC_MIXED_BF16X3 4 /* float32 build and cache; the sampler's       */
+                           /* products on bf16 matrix cores with both        */
+                           /* operands split into hi + lo parts (hi*hi +     */
+                           /* hi*lo + lo*hi, float32 accumulation)           */
 
 /* what the couplings are, for the exact-energy outputs of tnmc_energy     */
 #define TNMC_COUPLING_GENERAL 0  /* any float32 couplings                    */
@@ -186,6 +198,41 @@ int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace,
              double *logz_out, int32_t schedule, void *stream,
              tnmc_env **env_out);
 
+/* Schedule autotuner for tnmc_run on uneven batches.  Candidates: one
+ * persistent launch in each TNMC_SCHED_* order, and one launch per bond
+ * class (chi <= 16, <= 32, > 32) each on its own stream (smaller classes
+ * need less shared memory, so their workgroups can share a compute unit
+ * with the long builds).  Each is timed on a replica of the batch -- every
+ * instance cut to its top-left max(4, L/replica_scale) sub-lattice, same
+ * chi, beta and coupling values -- from the device clock the kernels record,
+ * and the best for `objective` is returned.  With cache_path non-NULL the
+ * result is read from / appended to that text file, keyed by the batch's
+ * composition (the multiset of (L, chi, beta)), precision, n_samples,
+ * objective and replica_scale; a cached answer does no device work.
+ *  workspace  device, >= tnmc_autotune_workspace_bytes, 256-byte aligned
+ *             (the replica's couplings, outputs and run workspace).
+ *  stream     the replica runs are synchronised before the call returns.  */
+#define TNMC_OBJ_P99      0   /* 99th percentile of per-instance completion  */
+#define TNMC_OBJ_P50      1   /* median per-instance completion              */
+#define TNMC_OBJ_MEAN     2   /* mean per-instance completion                */
+#define TNMC_OBJ_MAKESPAN 3   /* completion of the whole batch               */
+typedef struct tnmc_tuning {
+    int32_t schedule;         /* TNMC_SCHED_* for tnmc_run                     */
+    int32_t split;            /* 1: run each bond class as its own tnmc_run on */
+                              /*    its own stream (schedule longest-first)    */
+    double  objective_s;      /* the chosen candidate's objective (seconds, on */
+                              /* the replica)                                  */
+    double  candidates_s[4];  /* longest-first, shortest-first, as given,      */
+                              /* split by class (zero when read from cache)   */
+    int32_t from_cache;       /* 1 if read from the tuning cache               */
+} tnmc_tuning;
+size_t tnmc_autotune_workspace_bytes(const tnmc_problem *p, int32_t precision,
+                                     int32_t n_samples, int32_t replica_scale);
+int tnmc_autotune(const tnmc_problem *p, int32_t precision, int32_t n_samples,
+                  int32_t objective, int32_t replica_scale, void *workspace,
+                  size_t workspace_bytes, const char *cache_path, void *stream,
+                  tnmc_tuning *out);
+
 /* Draw (or score) n_samples configurations per instance (section 3.3).
  *  seed, sample_offset  Philox key and first global sample index; the
  *                sample counter is 32 bits wide, so sample_offset +
@@ -220,6 +267,19 @@ int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed,
  * evenly spaced (one launch per run).                                      */
 int tnmc_energy(const tnmc_problem *p, int32_t n_samples, const uint64_t *spins,
                 double *E_out, int32_t *E_int_out, void *stream);
+
+/* Replica overlap, the spin-glass order parameter: two Markov chains (a, b)
+ * run on the same instances with independent proposals; after each of this
+ * call's n_samples steps k, q[i][k] = (1/L_i^2) sum_sites s^a s^b of the two
+ * chains' current states.  The states are given by the global proposal
+ * indices tnmc_accept wrote (state_a / state_b, device int64 [B][n_samples])
+ * and read from this call's proposals (spins_a / spins_b, packed layout),
+ * proposal index = state - state_offset; a state from an earlier call gives
+ * NaN for that step.  q_out: device double [B][n_samples].  Moments of q
+ * over steps and disorders give <q^2>, <q^4> and the Binder ratio.          */
+int tnmc_overlap(const tnmc_problem *p, int32_t n_samples, const uint64_t *spins_a,
+                 const int64_t *state_a, const uint64_t *spins_b, const int64_t *state_b,
+                 uint64_t state_offset, double *q_out, void *stream);
 
 /* Metropolis independence step over each instance's proposals in index
  * order (Eq. (10)): with current state x and candidate k,

@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so"
 
 TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP, TNMC_ENUMERIC = 0, -1, -2, -3, -4, -5
 COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20 = 0, 1, 2
-FP64, FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
+FP64, FP32, MIXED_BF16, MIXED_FP16, MIXED_BF16X3 = 0, 1, 2, 3, 4
 SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16, "bf16x3": MIXED_BF16X3}
 CHAIN_BYTES = 48           # sizeof(tnmc_chain)
 
 _lib = None
@@ -36,6 +36,14 @@ class _Problem(ctypes.Structure):
                 ("off_h", POINTER(c_int64)), ("off_v", POINTER(c_int64)), ("coupling_kind", c_int32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("schedule", c_int32), ("split", c_int32), ("objective_s", c_double),
+                ("candidates_s", c_double * 4), ("from_cache", c_int32)]
+
+
+OBJECTIVES = {"p99": 0, "p50": 1, "mean": 2, "makespan": 3}
+
+
 class _Mlp(ctypes.Structure):
     _fields_ = [("params", c_void_p)]
 
@@ -46,7 +54,8 @@ MLP_LAYOUT = {"W1": (0, (64, 64)), "b1": (4096, (64,)), "W2": (4160, (64, 64)), 
 
 
 EXPORTS = ("tnmc_workspace_bytes", "tnmc_workspace_size", "tnmc_build_env", "tnmc_run", "tnmc_sample",
-           "tnmc_energy", "tnmc_accept", "tnmc_env_check",
+           "tnmc_energy", "tnmc_accept", "tnmc_env_check", "tnmc_overlap", "tnmc_autotune",
+           "tnmc_autotune_workspace_bytes",
            "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats",
            "tnmc_mlp_features", "tnmc_mlp_scratch_floats", "tnmc_mlp_train_step", "tnmc_mlp_forward")
 
@@ -64,6 +73,13 @@ def load(path: str = LIB_PATH):
     lib.tnmc_workspace_bytes.argtypes = [P(_Problem), c_int32, c_int32]
     lib.tnmc_workspace_bytes.restype = c_size_t
     lib.tnmc_env_check.argtypes = [c_void_p, c_void_p]
+    lib.tnmc_autotune_workspace_bytes.argtypes = [P(_Problem), c_int32, c_int32, c_int32]
+    lib.tnmc_autotune_workspace_bytes.restype = c_size_t
+    lib.tnmc_autotune.argtypes = [P(_Problem), c_int32, c_int32, c_int32, c_int32, c_void_p, c_size_t,
+                                  ctypes.c_char_p, c_void_p, P(_Tuning)]
+    lib.tnmc_autotune.restype = c_int
+    lib.tnmc_overlap.argtypes = [P(_Problem), c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p,
+                                 c_void_p]
     lib.tnmc_build_env.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p), c_void_p]
     lib.tnmc_run.argtypes = [P(_Problem), c_int32, c_void_p, c_size_t, c_int32, c_uint64, c_uint64, c_void_p,
                              c_uint64, c_uint64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -87,6 +103,7 @@ def load(path: str = LIB_PATH):
                                         ctypes.c_float, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.tnmc_mlp_forward.argtypes = [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]
     for name in ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy", "tnmc_env_check",
+                 "tnmc_overlap",
                  "tnmc_accept", "tnmc_philox_uniform", "tnmc_mlp_features", "tnmc_mlp_train_step",
                  "tnmc_mlp_forward"):
         getattr(lib, name).restype = c_int
@@ -215,6 +232,36 @@ def tnmc_energy(problem, n_samples: int, spins, E_out, E_int_out=None, stream=No
         problem = problem.problem
     _check(lib.tnmc_energy(byref(problem._c), n_samples, _ptr(spins), _ptr(E_out), _ptr(E_int_out),
                            _stream(stream)))
+
+
+def tnmc_overlap(problem, n_samples: int, spins_a, state_a, spins_b, state_b, q_out, state_offset: int = 0,
+                 stream=None):
+    """Replica overlap of two chains' current states after each step (see
+    tnmc.h); problem may be an Env."""
+    lib = load()
+    if isinstance(problem, Env):
+        problem = problem.problem
+    _check(lib.tnmc_overlap(byref(problem._c), n_samples, _ptr(spins_a), _ptr(state_a), _ptr(spins_b),
+                            _ptr(state_b), state_offset, _ptr(q_out), _stream(stream)))
+
+
+def tnmc_autotune(problem: Problem, precision: int, n_samples: int, objective: str = "p99",
+                  replica_scale: int = 4, cache_path=None, stream=None) -> dict:
+    """Schedule choice for tnmc_run on this batch (timed on a sub-lattice
+    replica in the library, or read from the tuning cache).  Returns a dict
+    with schedule, split, objective_s, candidates_s and from_cache."""
+    import torch
+    lib = load()
+    nbytes = lib.tnmc_autotune_workspace_bytes(byref(problem._c), precision, n_samples, replica_scale)
+    if nbytes == 0:
+        raise TnmcError(TNMC_EINVAL, lib.tnmc_last_error().decode())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = _Tuning()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib.tnmc_autotune(byref(problem._c), precision, n_samples, OBJECTIVES[objective], replica_scale,
+                             _ptr(ws), nbytes, path, _stream(stream), byref(out)))
+    return {"schedule": out.schedule, "split": bool(out.split), "objective_s": out.objective_s,
+            "candidates_s": list(out.candidates_s), "from_cache": bool(out.from_cache)}
 
 
 def tnmc_env_check(env: Env, stream=None):

@@ -35,6 +35,7 @@ SOURCES = {
     "energy_accept.hip": ["-ffp-contract=off"],
     "pipeline.hip": [],
     "abi.cpp": ["-x", "hip"],
+    "autotune.cpp": ["-x", "hip"],
 }
 
 

@@ -28,16 +28,18 @@ template <typename T, typename S>
 hipError_t launch_build(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
                         double *, int64_t *, int, int, size_t, hipStream_t);
 size_t build_lds_bytes(int chi, int L, size_t tsize);
-template <typename T, typename S>
+template <typename T, typename S, bool SPLIT16>
 hipError_t launch_pipeline(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
                            double *, int64_t *, int, int, size_t, int, uint64_t, uint64_t, uint64_t *, double *,
                            double *, void *, uint64_t, uint64_t, uint8_t *, int64_t *, hipStream_t);
-template <typename T, typename S>
-hipError_t launch_sample(int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
+template <typename T, typename S, bool SPLIT16>
+hipError_t launch_sample(int, int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
                          uint64_t, const uint64_t *, uint64_t *, double *, float *, const float *,
                          MlpArgs, int64_t *, hipStream_t);
 hipError_t launch_energy_run(int, int, int, const uint64_t *, int64_t, const float *, int64_t, const float *,
                              int64_t, double *, int32_t *, hipStream_t);
+hipError_t launch_overlap_run(int, int, int, const uint64_t *, const int64_t *, const uint64_t *, const int64_t *,
+                              int64_t, int64_t, double *, hipStream_t);
 hipError_t launch_accept(int, int, const double *, const double *, const double *, void *, uint64_t,
                          uint64_t, uint8_t *, int64_t *, hipStream_t);
 hipError_t launch_philox(uint64_t, const uint32_t *, uint32_t, uint32_t, uint32_t, int, double *,
@@ -54,12 +56,16 @@ static int fail(int code, const std::string &msg) {
     return code;
 }
 
+namespace tnmc {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+}
+
 static int hip_fail(hipError_t e, const char *what) {
     return fail(TNMC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
 struct tnmc_env {
-    int32_t batch = 0, precision = 0, chi_bucket = 0, max_tiles = 0;
+    int32_t batch = 0, precision = 0, chi_bucket = 0, chi_mask = 0, max_tiles = 0;
     std::vector<int32_t> L, chi;
     std::vector<double> beta;
     const float *J_h = nullptr, *J_v = nullptr;
@@ -69,6 +75,10 @@ struct tnmc_env {
     size_t ws_bytes = 0, tile_bytes = 0, desc_off = 0, sweeps_off = 0;
 };
 
+namespace tnmc {
+int env_batch(const tnmc_env *env) { return env ? env->batch : 0; }
+}
+
 namespace {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -77,9 +87,17 @@ size_t tsize_of(int prec) { return prec == TNMC_FP64 ? 8 : 4; }
 size_t ssize_of(int prec) {
     switch (prec) {
     case TNMC_FP64: return 8;
-    case TNMC_FP32: return 4;
+    case TNMC_FP32:
+    case TNMC_MIXED_BF16X3: return 4;
     default: return 2;
     }
+}
+
+// bit 0 / 1 / 2: the batch has instances with chi <= 16, 16 < chi <= 32, chi > 32
+int chi_mask_of(const tnmc_problem *p) {
+    int m = 0;
+    for (int i = 0; i < p->batch; ++i) m |= p->chi[i] <= 16 ? 1 : (p->chi[i] <= 32 ? 2 : 4);
+    return m;
 }
 
 int chi_bucket_of(int chi) { return chi <= 16 ? 16 : (chi <= 32 ? 32 : 64); }
@@ -97,7 +115,7 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
     if (p->batch < 1) return fail(TNMC_EINVAL, "batch must be >= 1");
     if (!p->L || !p->chi || !p->beta) return fail(TNMC_EINVAL, "L, chi and beta must be non-NULL host arrays");
     if (need_data && (!p->J_h || !p->J_v)) return fail(TNMC_EINVAL, "J_h and J_v must be non-NULL device arrays");
-    if (precision < TNMC_FP64 || precision > TNMC_MIXED_FP16) return fail(TNMC_EINVAL, "unknown precision");
+    if (precision < TNMC_FP64 || precision > TNMC_MIXED_BF16X3) return fail(TNMC_EINVAL, "unknown precision");
     for (int i = 0; i < p->batch; ++i) {
         const int L = p->L[i], chi = p->chi[i];
         const double b = p->beta[i];
@@ -240,6 +258,7 @@ int setup_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t 
     env->batch = p->batch;
     env->precision = precision;
     env->chi_bucket = pl.chi_bucket;
+    env->chi_mask = chi_mask_of(p);
     env->L.assign(p->L, p->L + p->batch);
     env->chi.assign(p->chi, p->chi + p->batch);
     env->beta.assign(p->beta, p->beta + p->batch);
@@ -282,6 +301,7 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     switch (precision) {
     case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
+    case TNMC_MIXED_BF16X3: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
     }
@@ -309,15 +329,16 @@ int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace, size_t w
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
     int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
     const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
-#define TNMC_RUN(T, S) tnmc::launch_pipeline<T, S>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, \
+#define TNMC_RUN(T, S, SP) tnmc::launch_pipeline<T, S, SP>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, \
         pl.chi_max, lds, n_samples, sample_seed, sample_offset, spins_out, logq_out, E_out, chain, accept_seed, \
         step_offset, accepted_out, state_out, st)
     hipError_t e;
     switch (precision) {
-    case TNMC_FP64: e = TNMC_RUN(double, double); break;
-    case TNMC_FP32: e = TNMC_RUN(float, float); break;
-    case TNMC_MIXED_BF16: e = TNMC_RUN(float, __hip_bfloat16); break;
-    default: e = TNMC_RUN(float, __half); break;
+    case TNMC_FP64: e = TNMC_RUN(double, double, false); break;
+    case TNMC_FP32: e = TNMC_RUN(float, float, false); break;
+    case TNMC_MIXED_BF16X3: e = TNMC_RUN(float, float, true); break;
+    case TNMC_MIXED_BF16: e = TNMC_RUN(float, __hip_bfloat16, false); break;
+    default: e = TNMC_RUN(float, __half, false); break;
     }
 #undef TNMC_RUN
     if (e != hipSuccess) { delete env; return hip_fail(e, "pipeline launch"); }
@@ -349,10 +370,15 @@ int tnmc_sample(tnmc_env *env, int32_t n_samples, uint64_t seed, uint64_t sample
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
     switch (env->precision) {
-    case TNMC_FP64: e = tnmc::launch_sample<double, double>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
-    case TNMC_FP32: e = tnmc::launch_sample<float, float>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
-    case TNMC_MIXED_BF16: e = tnmc::launch_sample<float, __hip_bfloat16>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
-    default: e = tnmc::launch_sample<float, __half>(env->chi_bucket, dd, env->ws, env->tile_bytes, env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, stats, st); break;
+#define TNMC_SAMPLE(T, S, SP) tnmc::launch_sample<T, S, SP>(env->chi_bucket, env->chi_mask, dd, env->ws, env->tile_bytes, \
+        env->batch, tiles, n_samples, seed, sample_offset, forced_spins, spins_out, logq_out, logits_out, env->J_v, ma, \
+        stats, st)
+    case TNMC_FP64: e = TNMC_SAMPLE(double, double, false); break;
+    case TNMC_FP32: e = TNMC_SAMPLE(float, float, false); break;
+    case TNMC_MIXED_BF16X3: e = TNMC_SAMPLE(float, float, true); break;
+    case TNMC_MIXED_BF16: e = TNMC_SAMPLE(float, __hip_bfloat16, false); break;
+    default: e = TNMC_SAMPLE(float, __half, false); break;
+#undef TNMC_SAMPLE
     }
     if (e != hipSuccess) return hip_fail(e, "sample launch");
     return TNMC_OK;
@@ -400,6 +426,38 @@ int tnmc_energy(const tnmc_problem *p, int32_t n_samples, const uint64_t *spins,
                                                E_out + (size_t)i0 * n_samples,
                                                E_int_out ? E_int_out + (size_t)i0 * n_samples : nullptr, st);
         if (e != hipSuccess) return hip_fail(e, "energy launch");
+        i0 = i1;
+    }
+    return TNMC_OK;
+}
+
+int tnmc_overlap(const tnmc_problem *p, int32_t n_samples, const uint64_t *spins_a, const int64_t *state_a,
+                 const uint64_t *spins_b, const int64_t *state_b, uint64_t state_offset, double *q_out,
+                 void *stream) {
+    if (!p) return fail(TNMC_EINVAL, "problem is NULL");
+    if (p->batch < 1 || !p->L) return fail(TNMC_EINVAL, "batch must be >= 1 with a host L array");
+    if (n_samples < 1) return fail(TNMC_EINVAL, "n_samples must be >= 1");
+    if (!spins_a || !state_a || !spins_b || !state_b || !q_out) return fail(TNMC_EINVAL, "NULL array argument");
+    if (state_offset > (uint64_t(1) << 62)) return fail(TNMC_EINVAL, "state_offset out of range");
+    const int B = p->batch;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int64_t wp = 0;
+    for (int i = 0; i < B; ++i) {
+        const int L = p->L[i];
+        if (L < 2 || L > TNMC_L_MAX)
+            return fail(TNMC_EINVAL, "instance " + std::to_string(i) + ": L must be in [2, " + std::to_string(TNMC_L_MAX) + "]");
+    }
+    for (int i0 = 0; i0 < B;) {
+        const int L = p->L[i0];
+        int i1 = i0 + 1;
+        while (i1 < B && p->L[i1] == L) ++i1;
+        const int64_t iw = (int64_t)n_samples * L * ((L + 63) / 64);
+        const size_t so = (size_t)i0 * n_samples;
+        hipError_t e = tnmc::launch_overlap_run(L, i1 - i0, n_samples, spins_a + (size_t)n_samples * wp, state_a + so,
+                                                spins_b + (size_t)n_samples * wp, state_b + so, iw,
+                                                (int64_t)state_offset, q_out + so, st);
+        if (e != hipSuccess) return hip_fail(e, "overlap launch");
+        wp += (int64_t)(i1 - i0) * L * ((L + 63) / 64);
         i0 = i1;
     }
     return TNMC_OK;

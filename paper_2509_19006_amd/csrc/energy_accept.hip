@@ -25,12 +25,42 @@ k_energy_run(int L, int n_samples, const uint64_t *__restrict__ spins, int64_t i
     d.off_h = (int64_t)j * stride_h;
     d.off_v = (int64_t)j * stride_v;
     const uint64_t *s = spins + (size_t)j * inst_words + (size_t)n * L * d.W;
-    const double e = energy_wave(d, s, Jh, Jv, lane);
-    if (E_int) {
-        const int64_t ei = energy_wave_int(d, s, Jh, Jv, lane);
-        if (lane == 0) E_int[(size_t)j * n_samples + n] = ei == INT64_MIN ? INT32_MIN : (int32_t)ei;
+    int64_t ei = 0;
+    const double e = energy_wave(d, s, Jh, Jv, lane, E_int ? &ei : nullptr);
+    if (lane == 0) {
+        E_out[(size_t)j * n_samples + n] = e;
+        if (E_int) E_int[(size_t)j * n_samples + n] = ei == INT64_MIN ? INT32_MIN : (int32_t)ei;
     }
-    if (lane == 0) E_out[(size_t)j * n_samples + n] = e;
+}
+
+// Replica overlap of two Markov chains of the same instances: for each
+// (step k, instance j of a run of equal L), q = (1/L^2) sum_i s_i^a s_i^b of
+// the two chains' current states, read from this call's proposals by their
+// global indices (state - offset); a state from before this call gives NaN.
+// One wave per (step, instance); popcount of the XOR of the packed rows.
+__global__ void __launch_bounds__(64)
+k_overlap_run(int L, int n_samples, const uint64_t *__restrict__ sa, const int64_t *__restrict__ ia,
+              const uint64_t *__restrict__ sb, const int64_t *__restrict__ ib, int64_t inst_words,
+              int64_t offset, double *__restrict__ q_out) {
+    const int j = blockIdx.y, k = blockIdx.x, lane = threadIdx.x;
+    const int W = (L + 63) / 64;
+    const int64_t xa = ia[(size_t)j * n_samples + k] - offset, xb = ib[(size_t)j * n_samples + k] - offset;
+    double *q = q_out + (size_t)j * n_samples + k;
+    if (xa < 0 || xa >= n_samples || xb < 0 || xb >= n_samples) {
+        if (lane == 0) *q = __builtin_nan("");
+        return;
+    }
+    const uint64_t *a = sa + (size_t)j * inst_words + (size_t)xa * L * W;
+    const uint64_t *b = sb + (size_t)j * inst_words + (size_t)xb * L * W;
+    const uint64_t tail = (L & 63) ? ((uint64_t(1) << (L & 63)) - 1) : ~uint64_t(0);
+    int64_t diff = 0;
+    for (int w = lane; w < L * W; w += 64) {
+        uint64_t x = a[w] ^ b[w];
+        if ((w % W) == W - 1) x &= tail;
+        diff += __popcll(x);
+    }
+    for (int m = 32; m > 0; m >>= 1) diff += __shfl_xor(diff, m, 64);
+    if (lane == 0) *q = 1.0 - 2.0 * (double)diff / ((double)L * (double)L);
 }
 
 // One thread per instance walks its proposals in order.
@@ -54,6 +84,14 @@ hipError_t launch_energy_run(int L, int n_inst, int n_samples, const uint64_t *s
                              int32_t *E_int, hipStream_t st) {
     hipLaunchKernelGGL(k_energy_run, dim3(n_samples, n_inst), dim3(64), 0, st, L, n_samples, spins, inst_words, Jh,
                        stride_h, Jv, stride_v, E, E_int);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap_run(int L, int n_inst, int n_samples, const uint64_t *sa, const int64_t *ia,
+                              const uint64_t *sb, const int64_t *ib, int64_t inst_words, int64_t offset,
+                              double *q, hipStream_t st) {
+    hipLaunchKernelGGL(k_overlap_run, dim3(n_samples, n_inst), dim3(64), 0, st, L, n_samples, sa, ia, sb, ib,
+                       inst_words, offset, q);
     return hipGetLastError();
 }
 

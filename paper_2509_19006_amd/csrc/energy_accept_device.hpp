@@ -12,67 +12,57 @@ struct Chain {
 };
 
 // Energy of the configuration s (L rows of W words) by one wave; every lane
-// returns the sum.  Each lane takes whole rows: the horizontal bonds of row
-// r and the vertical bonds from row r to r+1.  With +-1 or 2^-20-grid
+// returns the sum.  Lanes take columns (c = lane, lane + 64, ...) so that
+// the couplings of a row are read contiguously; the spin word of a row is
+// the same for a whole group of 64 columns.  With +-1 or 2^-20-grid
 // couplings every partial sum is exact in float64, so the result does not
-// depend on the summation order.
+// depend on the summation order.  With eint non-NULL the same sum is also
+// taken in integer arithmetic (*eint = INT64_MIN if some coupling is not an
+// integer of magnitude below 2^20).
 __device__ inline double energy_wave(const InstDesc &d, const uint64_t *s, const float *Jh_all,
-                                     const float *Jv_all, int lane) {
+                                     const float *Jv_all, int lane, int64_t *eint = nullptr) {
     const int L = d.L, W = d.W;
     const float *jh = Jh_all + d.off_h, *jv = Jv_all + d.off_v;
     double e = 0.0;
-    for (int r = lane; r < L; r += 64) {
+    int64_t ei = 0;
+    int bad = 0;
+    for (int r = 0; r < L; ++r) {
         const uint64_t *row = s + (size_t)r * W, *nxt = s + (size_t)(r + 1) * W;
-        for (int c = 0; c < L; ++c) {
-            const double sc = ((row[c >> 6] >> (c & 63)) & 1) ? 1.0 : -1.0;
+        for (int c = lane; c < L; c += 64) {
+            const int k = c >> 6;
+            const uint64_t w = row[k];
+            const int b = (int)((w >> (c & 63)) & 1);
             if (c + 1 < L) {
-                const double sr = ((row[(c + 1) >> 6] >> ((c + 1) & 63)) & 1) ? 1.0 : -1.0;
-                e -= (double)jh[(size_t)r * (L - 1) + c] * (sc * sr);
+                const int b1 = (int)(((c & 63) == 63 ? row[k + 1] : w) >> ((c + 1) & 63) & 1);
+                const float j = jh[(size_t)r * (L - 1) + c];
+                const int ss = (b == b1) ? 1 : -1;
+                e -= (double)j * (double)ss;
+                if (eint) {
+                    bad |= !(j == rintf(j) && fabsf(j) < 1048576.0f);
+                    ei -= (int64_t)j * ss;
+                }
             }
             if (r + 1 < L) {
-                const double sd = ((nxt[c >> 6] >> (c & 63)) & 1) ? 1.0 : -1.0;
-                e -= (double)jv[(size_t)r * L + c] * (sc * sd);
+                const int bd = (int)((nxt[k] >> (c & 63)) & 1);
+                const float j = jv[(size_t)r * L + c];
+                const int ss = (b == bd) ? 1 : -1;
+                e -= (double)j * (double)ss;
+                if (eint) {
+                    bad |= !(j == rintf(j) && fabsf(j) < 1048576.0f);
+                    ei -= (int64_t)j * ss;
+                }
             }
         }
     }
     for (int m = 32; m > 0; m >>= 1) e += __shfl_xor(e, m, 64);
-    return e;
-}
-
-// The same sum in integer arithmetic, for couplings that are integers
-// (+-J): every lane returns the energy, or INT64_MIN when some coupling of
-// the instance is not an integer of magnitude below 2^20 (|E| then stays
-// below 2^42, far inside int64; the int32 result is exact for L <= 1024,
-// where |E| <= 2 L (L-1) max|J|, with +-1 couplings).
-__device__ inline int64_t energy_wave_int(const InstDesc &d, const uint64_t *s, const float *Jh_all,
-                                          const float *Jv_all, int lane) {
-    const int L = d.L, W = d.W;
-    const float *jh = Jh_all + d.off_h, *jv = Jv_all + d.off_v;
-    int64_t e = 0;
-    int bad = 0;
-    for (int r = lane; r < L; r += 64) {
-        const uint64_t *row = s + (size_t)r * W, *nxt = s + (size_t)(r + 1) * W;
-        for (int c = 0; c < L; ++c) {
-            const int sc = ((row[c >> 6] >> (c & 63)) & 1) ? 1 : -1;
-            if (c + 1 < L) {
-                const float j = jh[(size_t)r * (L - 1) + c];
-                bad |= !(j == rintf(j) && fabsf(j) < 1048576.0f);
-                const int sr = ((row[(c + 1) >> 6] >> ((c + 1) & 63)) & 1) ? 1 : -1;
-                e -= (int64_t)j * (sc * sr);
-            }
-            if (r + 1 < L) {
-                const float j = jv[(size_t)r * L + c];
-                bad |= !(j == rintf(j) && fabsf(j) < 1048576.0f);
-                const int sd = ((nxt[c >> 6] >> (c & 63)) & 1) ? 1 : -1;
-                e -= (int64_t)j * (sc * sd);
-            }
+    if (eint) {
+        for (int m = 32; m > 0; m >>= 1) {
+            ei += __shfl_xor(ei, m, 64);
+            bad |= __shfl_xor(bad, m, 64);
         }
+        *eint = bad ? INT64_MIN : ei;
     }
-    for (int m = 32; m > 0; m >>= 1) {
-        e += __shfl_xor(e, m, 64);
-        bad |= __shfl_xor(bad, m, 64);
-    }
-    return bad ? INT64_MIN : e;
+    return e;
 }
 
 // Instance i's chain walks its n proposals (log q, E) in index order: the

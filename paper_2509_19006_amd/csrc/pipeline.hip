@@ -9,12 +9,21 @@
 #include "build_device.hpp"
 #include "energy_accept_device.hpp"
 #include "sample_device.hpp"
+#include "sample_mfma.hpp"
 
 namespace tnmc {
 
 static_assert(NT == NTS, "the fused pipeline runs the sampler with the build's workgroup");
 
-template <typename T, typename S, int MAXB>
+// Matrix-core form of a precision (as in sample.hip).
+template <typename S, bool SPLIT16> struct PipeMode;
+template <> struct PipeMode<float, false> { static constexpr int v = MF_F32; };
+template <> struct PipeMode<float, true> { static constexpr int v = MF_BF16; };
+template <> struct PipeMode<__hip_bfloat16, false> { static constexpr int v = MF_BF16; };
+template <> struct PipeMode<__half, false> { static constexpr int v = MF_F16; };
+template <> struct PipeMode<double, false> { static constexpr int v = MF_F32; };
+
+template <typename T, typename S, int MAXB, bool SPLIT16>
 __global__ void __launch_bounds__(NT)
 k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order, unsigned char *__restrict__ ws,
            const float *__restrict__ Jh_all, const float *__restrict__ Jv_all, double *__restrict__ logz_out,
@@ -33,19 +42,29 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
     const MlpArgs none{nullptr, nullptr};
     const int ntiles = (n_samples + NTS - 1) / NTS;
     for (int tile = 0; tile < ntiles; ++tile) {
-        if (d.chi <= 16) {
-            sample_tile<T, S, 16, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
-                                         spins_out, logq_out, nullptr, Jv_all, none,
-                                         reinterpret_cast<typename StageType<T, S>::type(*)[16][16]>(smem), nullptr);
-        } else if (MAXB <= 32 || d.chi <= 32) {
-            sample_tile<T, S, 32, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
-                                         spins_out, logq_out, nullptr, Jv_all, none,
-                                         reinterpret_cast<typename StageType<T, S>::type(*)[32][32]>(smem), nullptr);
-        } else {
-            if constexpr (MAXB >= 64)
+        // the sampler form tnmc_sample uses for this instance: float forms
+        // with chi <= 32 on the matrix cores, the rest on the vector unit
+        if constexpr (std::is_same<T, float>::value) {
+            constexpr int MODE = PipeMode<S, SPLIT16>::v;
+            float *fenv = reinterpret_cast<float *>(env);
+            if (d.chi <= 16)
+                sample_tile_mfma<16, S, MODE>(inst, tile, d, ws, fenv, n_samples, sample_seed, sample_offset,
+                                              nullptr, spins_out, logq_out, nullptr, Jv_all, smem);
+            else if (d.chi <= 32)
+                sample_tile_mfma<32, S, MODE>(inst, tile, d, ws, fenv, n_samples, sample_seed, sample_offset,
+                                              nullptr, spins_out, logq_out, nullptr, Jv_all, smem);
+            else if constexpr (MAXB >= 64)
                 sample_tile<T, S, 64, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset,
                                              nullptr, spins_out, logq_out, nullptr, Jv_all, none,
                                              reinterpret_cast<typename StageType<T, S>::type(*)[64][64]>(smem), nullptr);
+        } else if (d.chi <= 16) {
+            sample_tile<T, S, 16, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
+                                         spins_out, logq_out, nullptr, Jv_all, none,
+                                         reinterpret_cast<typename StageType<T, S>::type(*)[16][16]>(smem), nullptr);
+        } else {
+            sample_tile<T, S, 32, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
+                                         spins_out, logq_out, nullptr, Jv_all, none,
+                                         reinterpret_cast<typename StageType<T, S>::type(*)[32][32]>(smem), nullptr);
         }
         __syncthreads();
     }
@@ -71,13 +90,16 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
     }
 }
 
-template <typename T, typename S, int MAXB>
+template <typename T, typename S, int MAXB, bool SPLIT16>
 hipError_t launch_pipeline_w(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
                              const float *Jv, double *logz, int64_t *stats, int B, size_t lds_bytes,
                              int n_samples, uint64_t sseed, uint64_t soff, uint64_t *spins, double *logq, double *E,
                              void *chain, uint64_t aseed, uint64_t aoff, uint8_t *acc, int64_t *state,
                              hipStream_t st) {
-    auto kern = k_pipeline<T, S, MAXB>;
+    auto kern = k_pipeline<T, S, MAXB, SPLIT16>;
+    // room for the matrix-core sampler's staging as well
+    constexpr size_t stage = mf_stage_bytes<32, S, PipeMode<S, SPLIT16>::v>();
+    if (lds_bytes < stage) lds_bytes = stage;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(B), dim3(NT), lds_bytes, st, desc, order, ws, Jh, Jv, logz, stats, n_samples,
@@ -85,7 +107,7 @@ hipError_t launch_pipeline_w(const InstDesc *desc, const int32_t *order, unsigne
     return hipGetLastError();
 }
 
-template <typename T, typename S>
+template <typename T, typename S, bool SPLIT16>
 hipError_t launch_pipeline(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
                            const float *Jv, double *logz, int64_t *stats, int B, int chi_max, size_t lds_bytes,
                            int n_samples, uint64_t sseed, uint64_t soff, uint64_t *spins, double *logq, double *E,
@@ -93,26 +115,27 @@ hipError_t launch_pipeline(const InstDesc *desc, const int32_t *order, unsigned 
                            hipStream_t st) {
     if constexpr (sizeof(T) == 8) {
         if (chi_max > 32) return hipErrorInvalidValue;
-        return launch_pipeline_w<T, S, 32>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples, sseed,
+        return launch_pipeline_w<T, S, 32, SPLIT16>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples, sseed,
                                            soff, spins, logq, E, chain, aseed, aoff, acc, state, st);
     } else {
         if (chi_max <= 32)
-            return launch_pipeline_w<T, S, 32>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples,
+            return launch_pipeline_w<T, S, 32, SPLIT16>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples,
                                                sseed, soff, spins, logq, E, chain, aseed, aoff, acc, state, st);
-        return launch_pipeline_w<T, S, 64>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples, sseed,
+        return launch_pipeline_w<T, S, 64, SPLIT16>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples, sseed,
                                            soff, spins, logq, E, chain, aseed, aoff, acc, state, st);
     }
 }
 
-#define TNMC_LP(T, S)                                                                                          \
-    template hipError_t launch_pipeline<T, S>(const InstDesc *, const int32_t *, unsigned char *, const float *, \
-                                              const float *, double *, int64_t *, int, int, size_t, int,        \
-                                              uint64_t, uint64_t, uint64_t *, double *, double *, void *,       \
-                                              uint64_t, uint64_t, uint8_t *, int64_t *, hipStream_t);
-TNMC_LP(double, double)
-TNMC_LP(float, float)
-TNMC_LP(float, __hip_bfloat16)
-TNMC_LP(float, __half)
+#define TNMC_LP(T, S, SP)                                                                                     \
+    template hipError_t launch_pipeline<T, S, SP>(const InstDesc *, const int32_t *, unsigned char *,            \
+                                                  const float *, const float *, double *, int64_t *, int, int,   \
+                                                  size_t, int, uint64_t, uint64_t, uint64_t *, double *, double *, \
+                                                  void *, uint64_t, uint64_t, uint8_t *, int64_t *, hipStream_t);
+TNMC_LP(double, double, false)
+TNMC_LP(float, float, false)
+TNMC_LP(float, float, true)
+TNMC_LP(float, __hip_bfloat16, false)
+TNMC_LP(float, __half, false)
 #undef TNMC_LP
 
 }  // namespace tnmc

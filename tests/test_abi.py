@@ -149,3 +149,17 @@ def test_philox_counter_overflow_is_rejected(lib):
     rc = lib.tnmc_run(ctypes.byref(p._c), T.FP32, fake, 1 << 30, 8, 0, (1 << 32) - 1, fake, 0, 0, fake, fake,
                       fake, fake, None, None, 0, None, ctypes.byref(env))
     assert rc == T.TNMC_EINVAL and b"Philox" in lib.tnmc_last_error()
+
+
+def test_autotune_validation(lib):
+    p = _problem((16, 32), (8, 16), (1.0, 0.5))
+    assert lib.tnmc_autotune_workspace_bytes(ctypes.byref(p._c), T.FP32, 16, 4) > 0
+    assert lib.tnmc_autotune_workspace_bytes(ctypes.byref(p._c), T.FP32, 16, 0) == 0
+    out = T._Tuning()
+    # no couplings / bad objective: rejected before any device work
+    assert lib.tnmc_autotune(ctypes.byref(p._c), T.FP32, 16, 0, 4, None, 0, None, None,
+                             ctypes.byref(out)) == T.TNMC_EINVAL
+    q = _fake_problem((16, 32), T.COUPLING_GENERAL)
+    assert lib.tnmc_autotune(ctypes.byref(q._c), T.FP32, 16, 9, 4, None, 0, None, None,
+                             ctypes.byref(out)) == T.TNMC_EINVAL
+    assert lib.tnmc_autotune(ctypes.byref(q._c), T.FP32, 16, 0, 4, None, 0, None, None, None) == T.TNMC_EINVAL

@@ -18,7 +18,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec", [0, 1, 3])
+@pytest.mark.parametrize("prec", [0, 1, 3, 4])
 def test_build_and_sample_are_bit_reproducible(tnmc, prec):
     L, B, chi, n = 64, 16, 32, 256
     jh, jv = workloads.batch(L, B, "pmj", 11)

@@ -133,21 +133,41 @@ def test_zero_network_is_the_plain_proposal(tnmc):
         tnmc.tnmc_sample(run.env, n, 17, spins, logq, mlp=m)
         torch.cuda.synchronize()
         out.append((spins.cpu().numpy(), logq.cpu().numpy()))
-    # identical draws; log q equal to float32 rounding (the variant with the
-    # network is a separate compilation whose float32 contraction order may
-    # differ by an ulp)
+    # the plain proposal samples on the matrix cores, the one with the
+    # network on the vector unit (float32 both): draws identical, log q equal
+    # to float32 rounding of the two summation orders
     assert np.array_equal(out[0][0], out[1][0])
-    assert np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[0][1])) < 1e-6
+    assert np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[0][1])) < 2e-5
 
 
-def test_learned_proposal_is_trained_and_judged(tnmc):
-    """Train on high-chi conditionals of separately seeded disorders, then
-    judge the corrected low-chi proposal by acceptance on held-out disorders
-    against the plain one; the network is kept only if it wins, otherwise
-    the plain proposal is the fallback.  Either way the chosen proposal does
-    no worse than the plain one and sampling stays exact."""
+def test_selection_falls_back_to_the_plain_proposal(tnmc):
+    """The acceptance judge keeps a network only on a significant paired win:
+    an untrained network with a large random output (a correction that can
+    only hurt) is rejected, and the plain proposal's acceptances are what the
+    caller then samples with."""
     import torch
     import tnmc_gpu as G
+    from paper_2509_19006_amd import learned
+    L, beta, chi = 16, 1.0, 4
+    val_J = [workloads.instance(L, "gauss", 72, i) for i in range(8)]
+    G.say("learned correction: the judge rejects a harmful network")
+    P = _rand_params(torch, 9, out_scale=3.0)
+    chosen, a0, a1 = learned.select(val_J, chi, beta, P, n_samples=128, seed=12)
+    G.say(f"  acceptance plain {a0.mean():.4f}, with the random network {a1.mean():.4f}")
+    assert chosen is None
+    assert a1.mean() < a0.mean()
+
+
+@pytest.mark.xfail(strict=False, reason=(
+    "no measured gain yet: at 32x32, beta 1, chi 2 -> 16 the trained correction lowered the held-out "
+    "acceptance (0.2412 plain, 0.2287 with the network); at 1024x1024 the training loss stayed flat "
+    "(0.2794 -> 0.2797) -- the 5x5 window does not see what the truncation gets wrong"))
+def test_learned_proposal_gains_on_held_out_disorders(tnmc):
+    """Train on chi 16 conditionals of separately seeded disorders, then
+    require a paired acceptance gain of the corrected chi 2 proposal over
+    the plain one on 16 held-out disorders (one-sided Wilcoxon p < 0.01)."""
+    import tnmc_gpu as G
+    from scipy import stats
     from paper_2509_19006_amd import learned
     L, beta, lo_chi, hi_chi = 32, 1.0, 2, 16
     train_J = [workloads.instance(L, "gauss", 70, i) for i in range(16)]
@@ -156,9 +176,9 @@ def test_learned_proposal_is_trained_and_judged(tnmc):
     feat, lo, tgt = learned.make_training_data(train_J, lo_chi, hi_chi, beta, 32, seed=3)
     P, losses = learned.train(feat, lo, tgt, steps=400, batch=4096, lr=1e-3, seed=1, log=G.say)
     assert all(np.isfinite(l) for _, l in losses)
-    chosen, a0, a1 = learned.select(val_J, lo_chi, beta, P, n_samples=256, seed=11)
-    G.say(f"  acceptance plain {a0.mean():.4f}, with network {a1.mean():.4f}, "
-          f"kept: {chosen is not None}")
-    final = a1 if chosen is not None else a0
-    assert final.mean() >= a0.mean()
+    _, a0, a1 = learned.select(val_J, lo_chi, beta, P, n_samples=256, seed=11)
+    d = a1 - a0
+    pval = stats.wilcoxon(d, alternative="greater").pvalue if np.any(d != 0) else 1.0
+    G.say(f"  acceptance plain {a0.mean():.4f}, with network {a1.mean():.4f}, one-sided p {pval:.3g}")
     assert 0.0 < a0.mean() < 1.0
+    assert d.mean() > 0 and pval < 0.01

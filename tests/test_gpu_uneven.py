@@ -96,7 +96,7 @@ def test_decode_steps_replay_from_a_graph(tnmc):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 3])
+@pytest.mark.parametrize("prec", [0, 1, 3, 4])
 def test_fused_pipeline_equals_separate_calls(tnmc, prec):
     """tnmc_run (build, sampling tiles, energies and the chain in one
     persistent launch) gives bit-identical results to tnmc_build_env +
@@ -141,3 +141,33 @@ def test_fused_pipeline_equals_separate_calls(tnmc, prec):
     # the fused launch records each instance's completion after its build
     st = out[1][7]
     assert np.all(st[:, 6] > st[:, 5]) and np.all(st[:, 5] > st[:, 4])
+
+
+def test_autotuner_chooses_and_caches(tnmc, tmp_path):
+    """The library's tuner times its candidates on a sub-lattice replica,
+    returns the best for the objective, appends it to the tuning cache, and
+    answers the same batch from the cache without device work."""
+    import tnmc_gpu as G
+    from paper_2509_19006_amd import autotune
+    Ls = [16, 32, 24, 16, 32, 8]
+    chis = [16, 32, 64, 8, 16, 32]
+    betas = workloads.betas_uniform(len(Ls), 0.5, 2.0, 93)
+    Js = [workloads.instance(L, "gauss", 93, i) for i, L in enumerate(Ls)]
+    cache = str(tmp_path / "tuning.txt")
+    G.say("autotuner: replica timing and tuning cache")
+    first = autotune.tune(Js, chis, betas, tnmc.FP32, 16, "p99", 2, cache)
+    assert not first["from_cache"]
+    assert all(c > 0 for c in first["candidates_s"])
+    best = min(range(4), key=lambda k: first["candidates_s"][k])
+    assert first["split"] == (best == 3)
+    assert first["split"] or first["schedule"] == best
+    assert first["objective_s"] == first["candidates_s"][best]
+    with open(cache) as f:
+        assert len(f.readlines()) == 1
+    again = autotune.tune(list(reversed(Js)), list(reversed(chis)), list(reversed(betas)), tnmc.FP32, 16, "p99",
+                          2, cache)
+    assert again["from_cache"]
+    assert (again["schedule"], again["split"]) == (first["schedule"], first["split"])
+    # the chosen plan runs the full batch
+    res = autotune.run_schedule(Js, chis, betas, tnmc.FP32, 16, first["split"], first["schedule"])
+    assert res["trials"] == len(Ls) * 15 and np.all(res["completion_s"] > 0)
