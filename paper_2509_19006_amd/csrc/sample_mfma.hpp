@@ -122,19 +122,23 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
     float *wenv = env + (size_t)wave * 2 * JN * 64 + l;
     constexpr size_t ENV_C = (size_t)4 * 2 * JN * 64;   // floats per site of the tile
 
-    // ---- staging: the next site is fetched into registers while the
-    // current one is contracted, then stored (transposed for the left
-    // sweep, which reads the spin slices by column) ----
-    S pre[PER];
-    auto fetch = [&](const S *site) {
+    // ---- staging, two sites ahead: the entries of site k+2 are fetched
+    // into one register set while site k is contracted and site k+1 (fetched
+    // a step earlier) goes from the other set into the shared buffer the
+    // step before used (transposed for the left sweep, which reads the spin
+    // slices by column) ----
+    S pre[2][PER];
+    auto fetch = [&](auto SET, const S *site) {
+        constexpr int k = decltype(SET)::value;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + i * 256;
             const int s = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
-            pre[i] = (a < chi && b < chi) ? site[(size_t)s * chi * chi + a * chi + b] : S{};
+            pre[k][i] = (a < chi && b < chi) ? site[(size_t)s * chi * chi + a * chi + b] : S{};
         }
     };
-    auto put = [&](int buf, bool transposed) {
+    auto put = [&](auto SET, int buf, bool transposed) {
+        constexpr int k = decltype(SET)::value;
         E *dst = stage + buf * SITE;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -142,15 +146,17 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             const int s = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
             const int o = s * NP * SLICE + (transposed ? b * RS + a : a * RS + b);
             if constexpr (SPLIT) {
-                const float v = (float)pre[i];
+                const float v = (float)pre[k][i];
                 const E hi = (E)v;
                 dst[o] = hi;
                 dst[o + SLICE] = (E)(v - (float)hi);
             } else {
-                dst[o] = as_elem<E, S>(pre[i]);
+                dst[o] = as_elem<E, S>(pre[k][i]);
             }
         }
     };
+    using Set0 = std::integral_constant<int, 0>;
+    using Set1 = std::integral_constant<int, 1>;
 
     // per-lane state: the sample vectors of both column blocks
     float vec[2][JN];
@@ -165,12 +171,15 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             for (int j = 0; j < JN; ++j) vec[nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
         uint64_t uw = 0;
         int uw_idx = -1;
-        int buf = 0;
-        fetch(crow + (size_t)(L - 1) * site_sz);
-        put(0, false);
+        // step k contracts site c + 1 = L - 1 - k (c = L - 2 .. 0)
+        const int mR = L - 1;
+        fetch(Set0{}, crow + (size_t)(L - 1) * site_sz);
+        put(Set0{}, 0, false);
+        if (mR > 1) fetch(Set1{}, crow + (size_t)(L - 2) * site_sz);
         __syncthreads();
-        for (int c = L - 2; c >= 0; --c) {
-            if (c > 0) fetch(crow + (size_t)c * site_sz);
+        auto rstep = [&](int k, auto FS, auto PS) {
+            const int c = L - 2 - k, buf = k & 1;
+            if (k + 2 < mR) fetch(FS, crow + (size_t)(c - 1) * site_sz);
             const E *Ab = stage + buf * SITE;
             // vertical weights of both column blocks' samples at column c+1
             float w[2][2];
@@ -270,9 +279,12 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
                     ec[(size_t)j * 64] = vec[nb][j];
                 }
             }
-            if (c > 0) put(buf ^ 1, false);
+            if (k + 1 < mR) put(PS, buf ^ 1, false);
             __syncthreads();
-            buf ^= 1;
+        };
+        for (int k = 0; k < mR; k += 2) {
+            rstep(k, Set0{}, Set1{});
+            if (k + 1 < mR) rstep(k + 1, Set1{}, Set0{});
         }
         // ---------------- left sweep: sample row r ----------------
 #pragma unroll
@@ -280,12 +292,17 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
 #pragma unroll
             for (int j = 0; j < JN; ++j) vec[nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
         uint64_t cur = 0, up = 0, fw = 0;
-        buf = 0;
-        fetch(crow);
-        put(0, true);
+        fetch(Set0{}, crow);
+        put(Set0{}, 0, true);
+        if (L > 1) fetch(Set1{}, crow + site_sz);
         __syncthreads();
-        for (int c = 0; c < L; ++c) {
-            if (c + 1 < L) fetch(crow + (size_t)(c + 1) * site_sz);
+        auto lstep = [&](int c, auto FS, auto PS) {
+            const int buf = c & 1;
+            if (c + 2 < L) fetch(FS, crow + (size_t)(c + 2) * site_sz);
+            // the draw's uniform does not depend on the contraction: take it
+            // first, so that its latency hides behind the products
+            double u_draw = 0.0;
+            if (!my_forced) u_draw = philox_unit(seed, (uint32_t)(r * L + c), sidx, (uint32_t)inst, 0u);
             const E *Ab = stage + buf * SITE;
             // the site's right environment, in this lane's layout
             float renv[2][JN];
@@ -383,14 +400,16 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             const float mine1 = h ? part[1][1] : part[1][0], other1 = h ? part[1][0] : part[1][1];
             const float r0 = mine0 + __shfl_xor(other0, 32);
             const float r1 = mine1 + __shfl_xor(other1, 32);
-            const double rho0 = fabs((double)r0), rho1 = fabs((double)r1);
+            const float rho0 = fabsf(r0), rho1 = fabsf(r1);
             double logit = 0.0;
             if ((c & 63) == 0 && act) {
                 if (r > 0) up = my_out[(size_t)(r - 1) * W + (c >> 6)];
                 if (my_forced) fw = my_forced[(size_t)r * W + (c >> 6)];
             }
-            if (rho0 > 0.0 || rho1 > 0.0) {
-                logit = log(rho1 / rho0);
+            if (rho0 > 0.f || rho1 > 0.f) {
+                // the float32 ratio's logarithm in float32 (the products are
+                // float32); the conditional p is formed from it in float64
+                logit = (double)(logf(rho1) - logf(rho0));
                 if (r > 0) {
                     const double u = (double)((up >> (c & 63)) & 1);
                     logit += 2.0 * beta * (double)jv[(size_t)(r - 1) * L + c] * (2.0 * u - 1.0);
@@ -403,8 +422,7 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
                 spin = (int)((fw >> (c & 63)) & 1);
             } else {
                 const double p = (logit >= 0.0 ? 1.0 : ex) / (1.0 + ex);
-                const double u = philox_unit(seed, (uint32_t)(r * L + c), sidx, (uint32_t)inst, 0u);
-                spin = (u < p) ? 1 : 0;
+                spin = (u_draw < p) ? 1 : 0;
             }
             if (!act) spin = 0;
             logq += (spin ? fmin(logit, 0.0) : fmin(-logit, 0.0)) - l1p;
@@ -425,9 +443,12 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
 #pragma unroll
                 for (int j = 0; j < JN; ++j) vec[nb][j] = (sp[nb] ? yv(1, nb, j) : yv(0, nb, j)) * sc;
             }
-            if (c + 1 < L) put(buf ^ 1, true);
+            if (c + 1 < L) put(PS, buf ^ 1, true);
             __syncthreads();
-            buf ^= 1;
+        };
+        for (int c = 0; c < L; c += 2) {
+            lstep(c, Set0{}, Set1{});
+            if (c + 1 < L) lstep(c + 1, Set1{}, Set0{});
         }
     }
     if (act) logq_out[(size_t)inst * n_samples + my] = logq;
