@@ -326,6 +326,22 @@ int tnmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t n_r
                         float lr, int32_t step, float *scratch, float *grad_out,
                         float *loss_out, void *stream);
 
+/* tnmc_mlp_train_step without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid allocation): the partial gradients
+ * live in a static device array of the library, one per GPU for the life of
+ * the process, sized for n_rows <= TNMC_MLP_NOALLOC_MAX_ROWS (8.6 MB); more
+ * rows give TNMC_EINVAL.  The call allocates nothing.  Every call on a GPU
+ * shares that GPU's array and leaves it holding the last call's partials:
+ * calls that overlap on one GPU (concurrent streams, threads) race and must
+ * be serialised by the caller.  Results are bit-identical to
+ * tnmc_mlp_train_step with the same arguments.                             */
+#define TNMC_MLP_NOALLOC_MAX_ROWS 16384
+int tnmc_mlp_train_step_noalloc(float *params, float *adam_m, float *adam_v, int32_t n_rows,
+                                const float *feat, const float *logit_lo, const float *target_logit,
+                                float lr, int32_t step, float *grad_out, float *loss_out,
+                                void *stream);
+
 /* The correction d for n_rows feature rows (device float [n_rows]); with
  * bf16_weights != 0 the weights are first rounded to bfloat16, as inside
  * tnmc_sample.                                                            */

@@ -57,7 +57,8 @@ EXPORTS = ("tnmc_workspace_bytes", "tnmc_workspace_size", "tnmc_build_env", "tnm
            "tnmc_energy", "tnmc_accept", "tnmc_env_check", "tnmc_overlap", "tnmc_autotune",
            "tnmc_autotune_workspace_bytes",
            "tnmc_free_env", "tnmc_last_error", "tnmc_philox_uniform", "tnmc_env_stats",
-           "tnmc_mlp_features", "tnmc_mlp_scratch_floats", "tnmc_mlp_train_step", "tnmc_mlp_forward")
+           "tnmc_mlp_features", "tnmc_mlp_scratch_floats", "tnmc_mlp_train_step", "tnmc_mlp_forward",
+           "tnmc_mlp_train_step_noalloc")
 
 
 def load(path: str = LIB_PATH):
@@ -102,10 +103,12 @@ def load(path: str = LIB_PATH):
     lib.tnmc_mlp_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                         ctypes.c_float, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.tnmc_mlp_forward.argtypes = [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]
+    lib.tnmc_mlp_train_step_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                                c_void_p, ctypes.c_float, c_int32, c_void_p, c_void_p, c_void_p]
     for name in ("tnmc_workspace_size", "tnmc_build_env", "tnmc_sample", "tnmc_energy", "tnmc_env_check",
                  "tnmc_overlap",
                  "tnmc_accept", "tnmc_philox_uniform", "tnmc_mlp_features", "tnmc_mlp_train_step",
-                 "tnmc_mlp_forward"):
+                 "tnmc_mlp_forward", "tnmc_mlp_train_step_noalloc"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -336,6 +339,20 @@ def tnmc_mlp_train_step(params, adam_m, adam_v, feat, logit_lo, target_logit, lr
     _check(lib.tnmc_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), n, _ptr(feat), _ptr(logit_lo),
                                    _ptr(target_logit), float(lr), step, _ptr(scratch), _ptr(grad_out),
                                    _ptr(loss_out), _stream(stream)))
+
+
+MLP_NOALLOC_MAX_ROWS = 16384
+
+
+def tnmc_mlp_train_step_noalloc(params, adam_m, adam_v, feat, logit_lo, target_logit, lr: float, step: int,
+                                grad_out=None, loss_out=None, stream=None):
+    """tnmc_mlp_train_step with the library's static per-GPU scratch (at most
+    MLP_NOALLOC_MAX_ROWS rows; overlapping calls on one GPU race)."""
+    lib = load()
+    n = logit_lo.numel()
+    _check(lib.tnmc_mlp_train_step_noalloc(_ptr(params), _ptr(adam_m), _ptr(adam_v), n, _ptr(feat),
+                                           _ptr(logit_lo), _ptr(target_logit), float(lr), step, _ptr(grad_out),
+                                           _ptr(loss_out), _stream(stream)))
 
 
 def tnmc_mlp_forward(params, feat, d_out, bf16_weights: bool = False, stream=None):

@@ -22,6 +22,8 @@ hipError_t launch_mlp_features(const InstDesc *, int, int, int, const uint64_t *
 hipError_t launch_mlp_grad(const float *, int, const float *, const float *, const float *, float *, float *,
                            float *, float *, float *, float *, float, int, int, float *, hipStream_t);
 hipError_t launch_mlp_forward(const float *, int, const float *, int, float *, hipStream_t);
+hipError_t mlp_static_scratch(float **, size_t *);
+int mlp_static_max_rows();
 constexpr int kMlpRows = 64;
 constexpr int kMlpNParam = 8385;
 template <typename T, typename S>
@@ -525,6 +527,30 @@ int tnmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int32_t n_r
     hipError_t e = tnmc::launch_mlp_grad(params, n_rows, feat, logit_lo, target_logit, scratch,
                                          scratch + nblk * tnmc::kMlpNParam, adam_m, adam_v, grad_out, loss_out,
                                          lr, step, step > 0 ? 1 : 0, params, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mlp train launch");
+    return TNMC_OK;
+}
+
+int tnmc_mlp_train_step_noalloc(float *params, float *adam_m, float *adam_v, int32_t n_rows, const float *feat,
+                                const float *logit_lo, const float *target_logit, float lr, int32_t step,
+                                float *grad_out, float *loss_out, void *stream) {
+    if (!params || n_rows < 1 || !feat || !logit_lo || !target_logit || step < 0)
+        return fail(TNMC_EINVAL, "bad mlp_train_step_noalloc arguments");
+    if (n_rows > tnmc::mlp_static_max_rows())
+        return fail(TNMC_EINVAL, "n_rows " + std::to_string(n_rows) + " exceeds the static scratch limit of " +
+                                     std::to_string(tnmc::mlp_static_max_rows()) + " rows");
+    if (step > 0 && (!adam_m || !adam_v)) return fail(TNMC_EINVAL, "Adam moments are NULL");
+    if (!(lr >= 0.0f)) return fail(TNMC_EINVAL, "lr must be >= 0");
+    float *scr = nullptr;
+    size_t cap = 0;
+    hipError_t e = tnmc::mlp_static_scratch(&scr, &cap);
+    if (e != hipSuccess) return hip_fail(e, "static scratch lookup");
+    const size_t nblk = (size_t)(n_rows + tnmc::kMlpRows - 1) / tnmc::kMlpRows;
+    if (nblk * (tnmc::kMlpNParam + 1) > cap) return fail(TNMC_EINVAL, "static scratch too small");
+    // every partial is written before it is read: nothing needs clearing
+    e = tnmc::launch_mlp_grad(params, n_rows, feat, logit_lo, target_logit, scr, scr + nblk * tnmc::kMlpNParam,
+                              adam_m, adam_v, grad_out, loss_out, lr, step, step > 0 ? 1 : 0, params,
+                              static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "mlp train launch");
     return TNMC_OK;
 }

@@ -8,6 +8,8 @@
 //  k_mlp_reduce    sums the partial gradients in workgroup order, then
 //                  optionally applies one Adam step (Kingma & Ba, 2015)
 //  k_mlp_forward   the correction d for a batch of feature rows
+#include <mutex>
+
 #include "mlp_device.hpp"
 
 namespace tnmc {
@@ -172,6 +174,38 @@ k_mlp_forward(const float *__restrict__ P, int n, const float *__restrict__ feat
     for (int i = 0; i < MLP_IN; ++i) x[i] = feat[(size_t)row * MLP_IN + i];
     d_out[row] = mlp_forward(Ps, x);
 }
+
+// Scratch of the allocation-free training step: the per-workgroup partial
+// gradients and losses of up to kMlpStaticRows rows, one copy per GPU for the
+// life of the process.  Host code never passes this name to a kernel: it
+// takes the device address from mlp_static_scratch().
+constexpr int kMlpStaticRows = 16384;
+constexpr size_t kMlpStaticFloats = (size_t)(kMlpStaticRows / GR) * (MLP_NPARAM + 1);
+static __device__ __align__(256) float scratch[kMlpStaticFloats];
+
+// Device address of this GPU's copy of the static scratch, looked up once per
+// device (with that device current) and kept.  Returns the HIP error of the
+// lookup; *out receives the address and *floats its capacity.
+hipError_t mlp_static_scratch(float **out, size_t *floats) {
+    static std::mutex mu;
+    static float *addr[256] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<float *>(ptr);
+    }
+    *out = addr[dev];
+    *floats = kMlpStaticFloats;
+    return hipSuccess;
+}
+
+int mlp_static_max_rows() { return kMlpStaticRows; }
 
 size_t mlp_grad_lds_bytes() { return sizeof(float) * (MLP_NPARAM + 3 + 5 * GR * 65 + 2 * GR); }
 
