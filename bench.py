@@ -424,12 +424,12 @@ def run_paper(args):
 
 def run_sweep(args):
     """Acceptance against L, chi and beta on +-J EA lattices (the paper's
-    acceptance figure): for every (L, chi, beta) 16 disorders x 64 samples,
-    float32, run through the chunked driver."""
+    acceptance figure): per L, every (chi, beta, disorder) combination as one
+    uneven batch in one persistent launch (tnmc_run, float32), 16 disorders
+    x 64 samples each."""
     import numpy as np
     import torch
     import paper_2509_19006_amd as T
-    from paper_2509_19006_amd import chunked
     import workloads
     T.load()
     Ls = [8, 16, 32, 64, 128, 256, 512, 1024]
@@ -439,24 +439,115 @@ def run_sweep(args):
     table = []
     t0 = time.time()
     for L in Ls:
-        jh = torch.as_tensor(np.stack([workloads.instance(L, "pmj", 9, i)[0] for i in range(D)])).cuda()
-        jv = torch.as_tensor(np.stack([workloads.instance(L, "pmj", 9, i)[1] for i in range(D)])).cuda()
-        for chi in chis:
-            if L >= 1024 and chi > 16:
-                continue
-            for beta in betas:
-                res = chunked.run(jh, jv, L, chi, beta, T.FP32, N, 0x5A5A0009, coupling_kind=T.COUPLING_PMJ)
-                a = res["n_acc"] / np.maximum(1, res["n_trials"])
-                table.append({"L": L, "chi": chi, "beta": beta, "acceptance": float(a.mean()),
-                              "sd_over_disorders": float(a.std(ddof=1)), "wall_s": res["wall_s"]})
-                log(f"  L {L:5d} chi {chi:3d} beta {beta:.2f}: acceptance {a.mean():.4f} "
-                    f"(sd {a.std(ddof=1):.3f}), {res['wall_s']:.1f} s")
+        combos = [(chi, beta) for chi in chis for beta in betas if not (L >= 1024 and chi > 16)]
+        inst = [(chi, beta, d) for chi, beta in combos for d in range(D)]
+        Js = [workloads.instance(L, "pmj", 9, d) for d in range(D)]
+        jh = torch.as_tensor(np.concatenate([Js[d][0].ravel() for _, _, d in inst])).cuda()
+        jv = torch.as_tensor(np.concatenate([Js[d][1].ravel() for _, _, d in inst])).cuda()
+        p = T.Problem(jh, jv, [L] * len(inst), [c for c, _, _ in inst], [b for _, b, _ in inst],
+                      coupling_kind=T.COUPLING_PMJ)
+        B = len(inst)
+        ws = torch.empty(T.tnmc_workspace_size(p, T.FP32, N), dtype=torch.uint8, device="cuda")
+        spins = torch.empty(N * p.spin_words_per_sample(), dtype=torch.int64, device="cuda")
+        lq = torch.empty((B, N), dtype=torch.float64, device="cuda")
+        E = torch.empty((B, N), dtype=torch.float64, device="cuda")
+        acc = torch.empty((B, N), dtype=torch.uint8, device="cuda")
+        chain = torch.zeros(B * T.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
+        t1 = time.time()
+        env = T.tnmc_run(p, T.FP32, ws, N, 0x5A5A0009, chain, 0x5A5A000A, spins, lq, E, acc)
+        torch.cuda.synchronize()
+        T.tnmc_env_check(env)
+        wall = time.time() - t1
+        undefined_logz = int(T.tnmc_env_stats(env)[:, T.STAT_LOGZ_UNDEFINED].sum())
+        st = T.chain_state(chain.cpu().numpy())
+        a = np.array([c["n_acc"] / max(1, c["n_trials"]) for c in st])
+        for k, (chi, beta) in enumerate(combos):
+            ak = a[k * D:(k + 1) * D]
+            table.append({"L": L, "chi": chi, "beta": beta, "acceptance": float(ak.mean()),
+                          "sd_over_disorders": float(ak.std(ddof=1)), "wall_s_launch": wall})
+        if undefined_logz:
+            log(f"  L {L}: {undefined_logz} instance(s) with an undefined ln Z estimate (truncated total <= 0)")
+        log(f"  L {L:5d}: {B} instances in one launch, {wall:.1f} s; acceptance by (chi, beta): " +
+            ", ".join(f"{chi}/{beta}: {a[k * D:(k + 1) * D].mean():.3f}" for k, (chi, beta) in enumerate(combos)))
+        del env, ws, spins, lq, E, acc, chain, jh, jv
+        torch.cuda.empty_cache()
     line = {"metric": "acceptance rate against L, chi and beta (+-J EA, 16 disorders x 64 samples)",
             "value": None, "unit": "acceptance", "n_gpus": 1, "steps": 1, "warmup": 0,
             "ms_per_step": (time.time() - t0) * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "acceptance sweep: L in 8..1024, chi in 2..32, beta in {0.66, 1, 1.5}"},
+            "config": {"workload": "acceptance sweep: L in 8..1024, chi in 2..32 (to 16 at 1024), "
+                                   "beta in {0.66, 1, 1.5}, one uneven launch per L"},
             "table": table}
+    print(json.dumps(line), flush=True)
+
+
+def run_rbim(args):
+    """Random-bond Ising model along the Nishimori line: for each
+    antiferromagnetic fraction p, beta_N = ln((1-p)/p)/2, 64 disorders of
+    32 x 32 at chi 16 (float32), two independent chains of 256 proposals per
+    disorder.  Reports the disorder-averaged energy per bond of the chain
+    states against the exact -tanh(beta_N), the replica-overlap moments
+    [<q^2>], [<q^4>] and the Binder ratio, and the acceptance."""
+    import numpy as np
+    import torch
+    import paper_2509_19006_amd as T
+    import workloads
+    T.load()
+    L, chi, D, N = 32, 16, 64, 256
+    rows = []
+    t0 = time.time()
+    for pr in (0.05, 0.1, 0.15, 0.2, 0.25):
+        beta = 0.5 * math.log((1 - pr) / pr)
+        Js = [workloads.instance(L, "pmj", 12, d, p=pr) for d in range(D)]
+        jh = torch.as_tensor(np.stack([a for a, _ in Js])).cuda()
+        jv = torch.as_tensor(np.stack([b for _, b in Js])).cuda()
+        prob = T.Problem(jh, jv, [L] * D, chi, beta, coupling_kind=T.COUPLING_PMJ)
+        ws = torch.empty(T.tnmc_workspace_size(prob, T.FP32, N), dtype=torch.uint8, device="cuda")
+        env = T.tnmc_build_env(prob, T.FP32, ws)
+        bt = torch.full((D,), beta, dtype=torch.float64, device="cuda")
+        sp, st, en, na, ntr = [], [], [], 0, 0
+        for chain_seed in (0x5A5A0012, 0x5A5A0013):
+            spins = torch.empty(N * prob.spin_words_per_sample(), dtype=torch.int64, device="cuda")
+            lq = torch.empty((D, N), dtype=torch.float64, device="cuda")
+            E = torch.empty((D, N), dtype=torch.float64, device="cuda")
+            acc = torch.empty((D, N), dtype=torch.uint8, device="cuda")
+            state = torch.empty((D, N), dtype=torch.int64, device="cuda")
+            chain = torch.zeros(D * T.CHAIN_BYTES, dtype=torch.uint8, device="cuda")
+            T.tnmc_sample(env, N, chain_seed, spins, lq)
+            T.tnmc_energy(prob, N, spins, E)
+            T.tnmc_accept(lq, E, bt, chain, chain_seed, 0, acc, state)
+            sp.append(spins)
+            st.append(state)
+            en.append(torch.gather(E, 1, state))
+            c = T.chain_state(chain.cpu().numpy())
+            na += sum(x["n_acc"] for x in c)
+            ntr += sum(x["n_trials"] for x in c)
+        q = torch.empty((D, N), dtype=torch.float64, device="cuda")
+        T.tnmc_overlap(prob, N, sp[0], st[0], sp[1], st[1], q)
+        torch.cuda.synchronize()
+        T.tnmc_env_check(env)
+        nb = 2 * L * (L - 1)
+        e = torch.cat(en, 1).mean(1).cpu().numpy() / nb            # per disorder, per bond
+        qh = q.cpu().numpy()
+        q2 = (qh ** 2).mean(1)
+        q4 = (qh ** 4).mean(1)
+        rows.append({"p": pr, "beta_N": beta, "energy_per_bond": float(e.mean()),
+                     "energy_per_bond_err": float(e.std(ddof=1) / math.sqrt(D)),
+                     "exact_energy_per_bond": -math.tanh(beta),
+                     "q2": float(q2.mean()), "q4": float(q4.mean()),
+                     "binder": float(0.5 * (3.0 - q4.mean() / q2.mean() ** 2)),
+                     "acceptance": na / max(1, ntr)})
+        log(f"  p {pr:.2f} (beta_N {beta:.3f}): energy/bond {e.mean():.5f} +- {e.std(ddof=1) / math.sqrt(D):.5f} "
+            f"(exact {-math.tanh(beta):.5f}), [<q^2>] {q2.mean():.4f}, Binder {rows[-1]['binder']:.3f}, "
+            f"acceptance {rows[-1]['acceptance']:.4f}")
+        del env, ws
+    line = {"metric": "Nishimori-line RBIM observables (energy per bond vs exact, replica overlap)",
+            "value": None, "unit": "energy per bond", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": (time.time() - t0) * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"RBIM on the Nishimori line, {D} disorders of {L}x{L}, chi {chi}, "
+                                   f"two chains x {N} proposals"},
+            "table": rows}
     print(json.dumps(line), flush=True)
 
 
@@ -477,7 +568,8 @@ def main():
                          "fp32, bf16x3, fp16, bf16")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["headline", "uneven", "learned", "paper", "sweep"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "uneven", "learned", "paper", "sweep", "rbim"],
+                    default="headline",
                     help="headline: the 256x256 batch (default); uneven: the 512-instance mix in one "
                          "persistent launch with an autotuned schedule; learned: the learned correction "
                          "(use with --L 1024 --disorders 64 --samples 16)")
@@ -528,6 +620,9 @@ def main():
         return
     if args.workload == "sweep":
         run_sweep(args)
+        return
+    if args.workload == "rbim":
+        run_rbim(args)
         return
     import paper_2509_19006_amd as T
     import workloads

@@ -349,11 +349,15 @@ int tnmc_mlp_forward(const float *params, int32_t n_rows, const float *feat,
                      int32_t bf16_weights, float *d_out, void *stream);
 
 /* Numeric health of an env's build: synchronises the stream, then returns
- * TNMC_ENUMERIC if any instance has a row log-scale or ln Z that is not
- * finite, or a truncation whose one-sided Jacobi stopped at its sweep limit
- * (40 sweeps) before the columns were orthogonal to working precision;
+ * TNMC_ENUMERIC if any instance has a row log-scale that is not finite, or
+ * a truncation whose one-sided Jacobi stopped at its sweep limit (40
+ * sweeps) before the columns were orthogonal to working precision;
  * TNMC_OK otherwise.  tnmc_last_error() names the first such instance.
- * The counts per instance are slots 8 and 9 of tnmc_env_stats.             */
+ * The counts per instance are slots 8 and 9 of tnmc_env_stats.  A ln Z that
+ * is not finite with a sound cache is not an error: at small chi the
+ * truncated network's total (sum over every configuration) can come out
+ * zero or negative -- the estimate is undefined, sampling is unaffected --
+ * and slot 10 records it.                                                 */
 int tnmc_env_check(const tnmc_env *env, void *stream);
 
 /* Release an env (host memory only; the workspace stays the caller's).    */
@@ -378,7 +382,8 @@ int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
  * ended (the only tile when n_samples <= 256); the ticks spent in the
  * Householder factorisations (a part of the QR sweeps); the number of
  * truncations whose Jacobi reached the sweep limit; the number of row
- * log-scales (and ln Z) that are not finite; slots 10-15 are zero.  The
+ * log-scales that are not finite; 1 if ln Z is undefined (the truncated
+ * network's total was not positive); slots 11-15 are zero.  The
  * build processes instances in decreasing order of estimated cost
  * (L-1) L chi^3.
  * NULL for a NULL env.                                                    */

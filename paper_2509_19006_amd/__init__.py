@@ -290,7 +290,7 @@ def tnmc_philox_uniform(seed: int, c0, c1: int, c2: int, stream_id: int, out, st
 
 
 STATS_PER_INST = 16
-STAT_MAXSWEEP, STAT_NONFINITE = 8, 9
+STAT_MAXSWEEP, STAT_NONFINITE, STAT_LOGZ_UNDEFINED = 8, 9, 10
 
 
 def tnmc_env_stats(env: Env):
@@ -299,7 +299,8 @@ def tnmc_env_stats(env: Env):
     loops; build start and end ticks; end tick of the first sampling tile
     of the last tnmc_sample call; ticks in the Householder factorisations;
     truncations whose Jacobi reached the sweep limit; non-finite row
-    log-scales.  Synchronises the current stream."""
+    log-scales; 1 if ln Z is undefined (the truncated network's total was
+    not positive).  Synchronises the current stream."""
     import numpy as np
     import torch
     addr = load().tnmc_env_stats(env.handle)

@@ -476,7 +476,7 @@ int tnmc_env_check(const tnmc_env *env, void *stream) {
         const int64_t *s = st.data() + (size_t)tnmc::STATS_PER_INST * i;
         if (s[tnmc::STAT_NONFINITE])
             return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_NONFINITE]) +
-                                           " row log-scale(s) or ln Z not finite");
+                                           " row log-scale(s) not finite");
         if (s[tnmc::STAT_MAXSWEEP])
             return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_MAXSWEEP]) +
                                            " truncation(s) reached the Jacobi sweep limit");

@@ -142,24 +142,6 @@ template <> __device__ __forceinline__ double bperm<double>(int addr, double v) 
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Shared-memory accesses through the LDS address space (plain ds
-// instructions, no flat access and no wait after a store).  Two waves hand
-// data over with them in program order: the LDS unit serves one wave's
-// instructions in the order issued, so the only ordering to enforce is the
-// compiler's (lds_order).  lds_poll reads a word another wave writes, anew
-// on every call.
-template <typename U> __device__ __forceinline__ void lds_put(U *p, U v) {
-    *(__attribute__((address_space(3))) U *)p = v;
-}
-template <typename U> __device__ __forceinline__ U lds_get(const U *p) {
-    return *(const __attribute__((address_space(3))) U *)p;
-}
-__device__ __forceinline__ int lds_poll(const int *p) {
-    return __hip_atomic_load((const __attribute__((address_space(3))) int *)p, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
-
 // Rotation that makes columns with squared norms a, b and inner product c
 // orthogonal: with d = b - a and e = 2c, tan = sign(d) e / (|d| + sqrt(d^2 +
 // e^2)) (the smaller root of Rutishauser's quadratic, free of overflow for
@@ -250,35 +232,20 @@ template <bool IL, typename T> __device__ __forceinline__ T from_prev(T v, int d
 // reduction.  Pairs whose smaller column is below sqrt(n)*eps*||T||_F are
 // left alone: such columns are rounding noise and a relative orthogonality
 // test on them never settles.
-// The accumulated rotation W (from the identity) is carried either by the
-// same wave (OFF false) or by a second one (OFF, role 1) that replays the
-// steps as they are published: every step's (cos, sin) per group go to a ring
-// of two sweeps in shared memory (ring [2CHI][CHI/2][2]), then the step count
-// to ctl[0]; the replay reports its progress in ctl[1]; when the sweeps end
-// their total step count goes to ctl[2].  The shared-memory unit serves one
-// wave's accesses in order, so a published count is never seen before the
-// rotations it covers.  The block wave reuses a ring slot only once the
-// replay has passed it (in practice it never waits: the replay has less to
-// do per step).  Every wait is bounded; one that runs out sets ctl[3] and the
-// replay then returns W as NaN, so a lost stream shows in the results
-// instead of hanging the workgroup.  ctl = {published, replayed, total (-1
-// while running), error} must be {0, 0, -1, 0} on entry.
-// Both waves start from the columns ordered by decreasing norm (de Rijk's
-// pivoting, which shortens cyclic Jacobi), each computing the order from the
-// block.  On return the rotated block is back at Tb and W (n x n, same
+// The accumulated rotation W (from the identity) is carried by the same
+// wave, in registers beside the block.
+// The sweeps start from the columns ordered by decreasing norm (de Rijk's
+// pivoting, which shortens cyclic Jacobi).  On return the rotated block is back at Tb and W (n x n, same
 // leading dimension) at Wb, and the block wave writes the singular values
 // (column norms) of the positions to nrm_out[0, n): -1 for positions >= kr
 // and for an empty block.  Returns the sweep count (role 0).
-template <typename T, int CHI, bool IL, bool OFF>
-__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *ring, int *ctl,
-                          T *nrm_out, int kr) {
+template <typename T, int CHI, bool IL>
+__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *nrm_out, int kr) {
     static_assert(!IL || CHI == 32, "the interleaved layout rotates 16-lane rows");
-    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G, RING = 2 * CHI;
-    constexpr int WAIT_LIMIT = 1 << 22;   // polls of ~64 clocks: ~0.1 s
-    if (!OFF && role != 0) return 0;
+    constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
+    if (role != 0) return 0;
     typedef __attribute__((address_space(3))) T LT;
     LT *Tl = (LT *)Tb, *Wl = (LT *)Wb;
-    T *rv = ring;
     int g = IL ? (lane & 15) : lane / G, gl = IL ? (lane >> 4) : lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
     // pivoting: lane l < CHI measures column l, ranks it among all, and
@@ -314,44 +281,24 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
         src2 = (int)min((unsigned)__builtin_amdgcn_ds_bpermute((2 * g) << 2, colpos), (unsigned)CHI);
         src3 = (int)min((unsigned)__builtin_amdgcn_ds_bpermute((2 * g + 1) << 2, colpos), (unsigned)CHI);
     }
-    const bool blk = role == 0;
-    // x, y: the pair's columns (block, or W in the replay wave); wx, wy: W
-    // in the block wave when it carries W itself
-    T x[RK], y[RK], wx[OFF ? 1 : RK], wy[OFF ? 1 : RK];
+    // x, y: the pair's columns of the block; wx, wy: the same columns of W
+    T x[RK], y[RK], wx[RK], wy[RK];
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
-        if (blk) {
-            x[i] = (row < K && src2 < n) ? Tl[src2 * ld + row] : (T)0;
-            y[i] = (row < K && src3 < n) ? Tl[src3 * ld + row] : (T)0;
-        } else {
-            x[i] = (row == src2) ? (T)1 : (T)0;
-            y[i] = (row == src3) ? (T)1 : (T)0;
-        }
-        if constexpr (!OFF) {
-            wx[i] = (row == src2) ? (T)1 : (T)0;
-            wy[i] = (row == src3) ? (T)1 : (T)0;
-        }
+        x[i] = (row < K && src2 < n) ? Tl[src2 * ld + row] : (T)0;
+        y[i] = (row < K && src3 < n) ? Tl[src3 * ld + row] : (T)0;
+        wx[i] = (row == src2) ? (T)1 : (T)0;
+        wy[i] = (row == src3) ? (T)1 : (T)0;
     }
     const int up = ((lane + G) & 63) << 2, dn = ((lane - G) & 63) << 2;
     const bool last = (g == HP - 1);
     int sweeps = 0;
-    if (blk) {
+    {
         const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
         const T tol2 = tol * tol;
         T small = 0;
-        int t = 0, slot = 0;
         for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
-            if constexpr (OFF) {
-                // this sweep reuses the slots of the sweep before the last one
-                if (sw >= 2) {
-                    int polls = 0;
-                    while (lds_poll(ctl + 1) < t - CHI) {
-                        if (++polls > WAIT_LIMIT) { lds_put(ctl + 3, 1); break; }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-            }
             T a = 0, b = 0;
 #pragma unroll
             for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
@@ -371,35 +318,21 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
                     const T c = pair_sum<IL>(c0 + c1, G);
                     T cs, sn;
                     rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
-                    if constexpr (OFF) {
-                        // every lane writes: a group's lanes store the same
-                        // values to the same words (a lane mask here would
-                        // split the step into basic blocks the scheduler
-                        // cannot overlap)
-                        lds_put(rv + (slot * HP + g) * 2, cs);
-                        lds_put(rv + (slot * HP + g) * 2 + 1, sn);
-                        lds_order();
-                        lds_put(ctl, t + 1);
-                        ++t;
-                        slot = slot + 1 == RING ? 0 : slot + 1;
-                    }
 #pragma unroll
                     for (int i = 0; i < RK; ++i) {
                         const T u = x[i], v = y[i];
                         x[i] = cs * u - sn * v;
                         y[i] = sn * u + cs * v;
-                        if constexpr (!OFF) {
-                            const T p = wx[i], q = wy[i];
-                            wx[i] = cs * p - sn * q;
-                            wy[i] = sn * p + cs * q;
-                        }
+                        const T p = wx[i], q = wy[i];
+                        wx[i] = cs * p - sn * q;
+                        wy[i] = sn * p + cs * q;
                     }
                     if (!odd) {
                         // even -> odd layout: second column from the next group
 #pragma unroll
                         for (int i = 0; i < RK; ++i) {
                             y[i] = from_next<IL>(y[i], up);
-                            if constexpr (!OFF) wy[i] = from_next<IL>(wy[i], up);
+                            wy[i] = from_next<IL>(wy[i], up);
                         }
                         b = from_next<IL>(b, up);
                     } else {
@@ -408,7 +341,7 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
 #pragma unroll
                         for (int i = 0; i < RK; ++i) {
                             x[i] = from_prev<IL>(x[i], dn);
-                            if constexpr (!OFF) wx[i] = from_prev<IL>(wx[i], dn);
+                            wx[i] = from_prev<IL>(wx[i], dn);
                         }
                         a = from_prev<IL>(a, dn);
                     }
@@ -417,80 +350,11 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
             ++sweeps;
             if (__ballot(rot) == 0) break;
         }
-        if constexpr (OFF) {
-            lds_order();
-            if (lane == 0) lds_put(ctl + 2, t);
-        }
-    } else if constexpr (OFF) {
-        // replay in batches of RB published steps: the rotations of a batch
-        // are read together, and a wait costs one poll per batch, not per
-        // step
-        constexpr int RB = 4;
-        int t = 0, slot = 0;
-        bool bad = false;
-        for (;;) {
-            // wait for RB more steps, or for the end
-            int polls = 0, avail = 0;
-            for (;;) {
-                // the total is read before the count: once set, the count
-                // already covers it
-                const int f = lds_poll(ctl + 2);
-                lds_order();
-                const int pcount = lds_poll(ctl);
-                if (pcount >= t + RB || (f >= 0 && pcount > t)) { avail = pcount - t; break; }
-                if (f >= 0 && t >= f) break;
-                if (lds_poll(ctl + 3) || ++polls > WAIT_LIMIT) { bad = true; break; }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (avail == 0) break;
-            lds_order();
-            while (avail > 0) {
-                const int nb = avail < RB ? avail : RB;
-                T cs[RB], sn[RB];
-#pragma unroll
-                for (int j = 0; j < RB; ++j) {
-                    int sj = slot + j;
-                    sj = sj >= RING ? sj - RING : sj;
-                    cs[j] = j < nb ? lds_get(rv + (sj * HP + g) * 2) : (T)1;
-                    sn[j] = j < nb ? lds_get(rv + (sj * HP + g) * 2 + 1) : (T)0;
-                }
-#pragma unroll
-                for (int j = 0; j < RB; ++j) {
-                    if (j < nb) {
-#pragma unroll
-                        for (int i = 0; i < RK; ++i) {
-                            const T u = x[i], v = y[i];
-                            x[i] = cs[j] * u - sn[j] * v;
-                            y[i] = sn[j] * u + cs[j] * v;
-                        }
-                        if (((t + j) & 1) == 0) {
-#pragma unroll
-                            for (int i = 0; i < RK; ++i) y[i] = from_next<IL>(y[i], up);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < RK; ++i) x[i] = from_prev<IL>(x[i], dn);
-                        }
-                    }
-                }
-                t += nb;
-                slot += nb;
-                slot = slot >= RING ? slot - RING : slot;
-                avail -= nb;
-                lds_order();
-                if (lane == 0) lds_put(ctl + 1, t);
-            }
-        }
-        if (bad || lds_poll(ctl + 3)) {
-            lds_put(ctl + 3, 1);
-#pragma unroll
-            for (int i = 0; i < RK; ++i) { x[i] = __builtin_nan(""); y[i] = __builtin_nan(""); }
-        }
-        sweeps = t / CHI;
     }
     // after an odd number of sweeps the positions are reversed
     const bool rev = sweeps & 1;
     const int cx = rev ? CHI - 1 - 2 * g : 2 * g, cy = rev ? CHI - 2 - 2 * g : 2 * g + 1;
-    if (blk) {
+    {
         // singular values from the registers (rows >= K hold zeros)
         T sx[2] = {0, 0}, sy[2] = {0, 0};
 #pragma unroll
@@ -504,23 +368,16 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
 #pragma unroll
     for (int i = 0; i < RK; ++i) {
         const int row = gl + G * i;
-        if (blk) {
-            if (row < K) {
-                if (cx < n) Tl[cx * ld + row] = x[i];
-                if (cy < n) Tl[cy * ld + row] = y[i];
-            }
-            if constexpr (!OFF) {
-                if (row < n) {
-                    if (cx < n) Wl[cx * ld + row] = wx[i];
-                    if (cy < n) Wl[cy * ld + row] = wy[i];
-                }
-            }
-        } else if (row < n) {
-            if (cx < n) Wl[cx * ld + row] = x[i];
-            if (cy < n) Wl[cy * ld + row] = y[i];
+        if (row < K) {
+            if (cx < n) Tl[cx * ld + row] = x[i];
+            if (cy < n) Tl[cy * ld + row] = y[i];
+        }
+        if (row < n) {
+            if (cx < n) Wl[cx * ld + row] = wx[i];
+            if (cy < n) Wl[cy * ld + row] = wy[i];
         }
     }
-    return blk ? sweeps : 0;
+    return sweeps;
 }
 
 // One-sided (Hestenes) Jacobi on one block with the block in one wave's
@@ -666,17 +523,14 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
 // waves also write the singular values to nrm_out (see jacobi_reg).
 template <typename T, int MAXB>
 __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
-                            int *flags, T *ring, int *ctl, T *nrm_out, int kr) {
+                            int *flags, T *nrm_out, int kr) {
     if constexpr (MAXB >= 64) {
         if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
     }
     // chi <= 16: contiguous groups; chi <= 32: interleaved groups; W in the
-    // block's wave (the replay form, OFF, is not dispatched: with it the
-    // float64 build differed between runs at rounding level, also with
-    // release / acquire fences around the published count, for a reason
-    // not yet found)
-    if (chi <= 16) return jacobi_reg<T, 16, false, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
-    return jacobi_reg<T, 32, true, false>(Tb, Wb, ld, K, n, lane, role, ring, ctl, nrm_out, kr);
+    // block's wave
+    if (chi <= 16) return jacobi_reg<T, 16, false>(Tb, Wb, ld, K, n, lane, role, nrm_out, kr);
+    return jacobi_reg<T, 32, true>(Tb, Wb, ld, K, n, lane, role, nrm_out, kr);
 }
 
 // Sum over a lane's rows of a[r] * b[r] in four independent partial sums
@@ -1273,7 +1127,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 }
                 const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
                                                      tid & 63, wv >> 1, pb, jprm, jflag,
-                                                     nullptr, nullptr, nrm + pb * n, kr);
+                                                     nrm + pb * n, kr);
                 if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
                 total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
@@ -1392,12 +1246,12 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
         double lz = logz_tail;
         int nonfinite = 0;
         for (int r = 0; r < L; ++r) { lz += lsc[r]; nonfinite += !isfinite(lsc[r]); }
-        nonfinite += !isfinite(lz);
         if (logz_out) logz_out[inst] = lz;
         if (stats_out) {
             int64_t *so = stats_out + STATS_PER_INST * inst;
             so[STAT_MAXSWEEP] = maxsweep_hits;
             so[STAT_NONFINITE] = nonfinite;
+            so[STAT_LOGZ_UNDEFINED] = nonfinite == 0 && !isfinite(lz);
             so[0] = total_sweeps;
             so[1] = cyc_qr;
             so[2] = cyc_svd;

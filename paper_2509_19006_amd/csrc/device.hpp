@@ -28,9 +28,11 @@ static_assert(sizeof(InstDesc) == 96, "InstDesc layout");
 // tick of the instance's last sampling tile, ticks in the Householder
 // factorisations (part of the QR sweeps); then the numeric-failure counts:
 // truncations whose Jacobi stopped at the sweep limit without converging,
-// and rows whose log-scale (or the final ln Z) is not finite.
+// and rows whose log-scale is not finite; then 1 if the truncated network's
+// total (the contraction that gives ln Z) was not positive, so that ln Z is
+// not finite while the cache itself is sound.
 constexpr int STATS_PER_INST = 16;
-constexpr int STAT_MAXSWEEP = 8, STAT_NONFINITE = 9;
+constexpr int STAT_MAXSWEEP = 8, STAT_NONFINITE = 9, STAT_LOGZ_UNDEFINED = 10;
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) -----------------------------------
 struct U4 { uint32_t x, y, z, w; };

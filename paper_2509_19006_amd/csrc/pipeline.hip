@@ -98,7 +98,7 @@ hipError_t launch_pipeline_w(const InstDesc *desc, const int32_t *order, unsigne
                              hipStream_t st) {
     auto kern = k_pipeline<T, S, MAXB, SPLIT16>;
     // room for the matrix-core sampler's staging as well
-    constexpr size_t stage = mf_stage_bytes<32, S, PipeMode<S, SPLIT16>::v>();
+    constexpr size_t stage = mf_lds_bytes<32, S, PipeMode<S, SPLIT16>::v>();
     if (lds_bytes < stage) lds_bytes = stage;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;

@@ -18,7 +18,7 @@ k_sample_mfma(const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
     const InstDesc d = desc[inst];
     // this launch takes the instances with chi_lo < chi <= CHI
     if (d.chi <= chi_lo || d.chi > CHI) return;
-    __shared__ __align__(16) unsigned char stage[mf_stage_bytes<CHI, S, MODE>()];
+    __shared__ __align__(16) unsigned char stage[mf_lds_bytes<CHI, S, MODE>()];
     float *env = reinterpret_cast<float *>(ws + d.env_off + (size_t)tile * tile_bytes);
     sample_tile_mfma<CHI, S, MODE>(inst, tile, d, ws, env, n_samples, seed, sample_offset, forced, spins_out,
                                    logq_out, logits_out, Jv_all, stage);

@@ -84,10 +84,16 @@ template <int CHI, typename S, int MODE> __host__ __device__ constexpr size_t mf
     using E = typename MfElem<MODE>::E;
     return (size_t)2 * (SplitA<S, MODE>::value ? 2 : 1) * 2 * CHI * mf_row<CHI, S, MODE>() * sizeof(E);
 }
+// ... plus the row's vertical-bond tables (two float weights and one double
+// coupling term per column, up to 1024 columns)
+constexpr size_t MF_ROW_TABLE_BYTES = (size_t)16 * 1024;
+template <int CHI, typename S, int MODE> __host__ __device__ constexpr size_t mf_lds_bytes() {
+    return mf_stage_bytes<CHI, S, MODE>() + MF_ROW_TABLE_BYTES;
+}
 
 // One tile of 256 samples of instance inst; all 256 threads call it.
 // env: the tile's right-environment scratch (L * CHI * 256 floats).
-// smem: at least mf_stage_bytes<CHI, S, MODE>() bytes, 16-byte aligned.
+// smem: at least mf_lds_bytes<CHI, S, MODE>() bytes, 16-byte aligned.
 template <int CHI, typename S, int MODE>
 __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const unsigned char *__restrict__ ws,
                                  float *__restrict__ env, int n_samples, uint64_t seed, uint64_t sample_offset,
@@ -118,6 +124,10 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
     float *my_logits = logits_out ? logits_out + (size_t)n_samples * d.site_prefix + (size_t)my * L * L : nullptr;
     const uint32_t sidx = (uint32_t)(sample_offset + (uint64_t)my);
     E *stage = reinterpret_cast<E *>(smem);
+    // vertical bonds from row r-1: Boltzmann weights of equal / opposite
+    // spins (the right sweep's w) and 2 beta J (the left sweep's logit term)
+    double *ctab = reinterpret_cast<double *>(smem + mf_stage_bytes<CHI, S, MODE>());
+    float *wtab = reinterpret_cast<float *>(ctab + L);
     // this wave's slice of the scratch: [c][JN * 2 registers][64 lanes]
     float *wenv = env + (size_t)wave * 2 * JN * 64 + l;
     constexpr size_t ENV_C = (size_t)4 * 2 * JN * 64;   // floats per site of the tile
@@ -171,6 +181,16 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             for (int j = 0; j < JN; ++j) vec[nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
         uint64_t uw = 0;
         int uw_idx = -1;
+        if (r > 0) {
+            for (int c = tid; c < L; c += 256) {
+                const float J = jv[(size_t)(r - 1) * L + c];
+                double same, diff;
+                boltz(beta, J, same, diff);
+                wtab[2 * c] = (float)same;
+                wtab[2 * c + 1] = (float)diff;
+                ctab[c] = 2.0 * beta * (double)J;
+            }
+        }
         // step k contracts site c + 1 = L - 1 - k (c = L - 2 .. 0)
         const int mR = L - 1;
         fetch(Set0{}, crow + (size_t)(L - 1) * site_sz);
@@ -192,14 +212,13 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
                         u = (int)((uw >> (cc & 63)) & 1);
                     }
                     const int u_other = __shfl_xor(u, 32);
-                    double same, diff;
-                    boltz(beta, jv[(size_t)(r - 1) * L + cc], same, diff);
+                    const float same = wtab[2 * cc], diff = wtab[2 * cc + 1];
                     // own block h, the other block 1 - h
                     const int ub[2] = {h ? u_other : u, h ? u : u_other};
 #pragma unroll
                     for (int nb = 0; nb < 2; ++nb) {
-                        w[0][nb] = (float)(ub[nb] == 0 ? same : diff);
-                        w[1][nb] = (float)(ub[nb] == 1 ? same : diff);
+                        w[0][nb] = ub[nb] == 0 ? same : diff;
+                        w[1][nb] = ub[nb] == 1 ? same : diff;
                     }
                 } else {
 #pragma unroll
@@ -292,9 +311,27 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
 #pragma unroll
             for (int j = 0; j < JN; ++j) vec[nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
         uint64_t cur = 0, up = 0, fw = 0;
+        // right environments, one site ahead, through two register sets
+        float renvs[2][2][JN];
+        auto load_env = [&](auto SET, int c) {
+            constexpr int k = decltype(SET)::value;
+            if (c < L - 1) {
+                const float *ec = wenv + (size_t)c * ENV_C;
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                    for (int j = 0; j < JN; ++j) renvs[k][nb][j] = ec[(size_t)(nb * JN + j) * 64];
+            } else {
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                    for (int j = 0; j < JN; ++j) renvs[k][nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
+            }
+        };
         fetch(Set0{}, crow);
         put(Set0{}, 0, true);
         if (L > 1) fetch(Set1{}, crow + site_sz);
+        load_env(Set0{}, 0);
         __syncthreads();
         auto lstep = [&](int c, auto FS, auto PS) {
             const int buf = c & 1;
@@ -304,20 +341,11 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             double u_draw = 0.0;
             if (!my_forced) u_draw = philox_unit(seed, (uint32_t)(r * L + c), sidx, (uint32_t)inst, 0u);
             const E *Ab = stage + buf * SITE;
-            // the site's right environment, in this lane's layout
-            float renv[2][JN];
-            if (c < L - 1) {
-                const float *ec = wenv + (size_t)c * ENV_C;
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                    for (int j = 0; j < JN; ++j) renv[nb][j] = ec[(size_t)(nb * JN + j) * 64];
-            } else {
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-                    for (int j = 0; j < JN; ++j) renv[nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
-            }
+            // the site's right environment (loaded a step earlier, in this
+            // lane's layout); the next site's is fetched now
+            constexpr int KE = decltype(FS)::value;
+            const float (&renv)[2][JN] = renvs[KE];
+            if (c + 1 < L) load_env(PS, c + 1);
             // y[s] for both column blocks: MB result tiles of 32 rows
             constexpr int MB = CHI == 32 ? 2 : 1;
             f32x16 acc[MB][2];
@@ -412,7 +440,7 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
                 logit = (double)(logf(rho1) - logf(rho0));
                 if (r > 0) {
                     const double u = (double)((up >> (c & 63)) & 1);
-                    logit += 2.0 * beta * (double)jv[(size_t)(r - 1) * L + c] * (2.0 * u - 1.0);
+                    logit += ctab[c] * (2.0 * u - 1.0);
                 }
             }
             const double ex = exp(-fabs(logit));

@@ -280,3 +280,20 @@ def test_degenerate_weights_give_the_uniform_law(G, tnmc, prec):
         acc, _, _ = G.gpu_accept(lq, run.energy(sp), np.full(len(inst), beta), 3, 0)
         if beta == 0.0:
             assert acc.all()
+
+
+def test_undefined_logz_estimate_is_not_a_cache_failure(G, tnmc):
+    """At chi = 2 the truncated network's total (every configuration summed)
+    of this +-J 64x64 instance at beta 1.5 is not positive -- the oracle's
+    log of it fails too (tests/test_oracle_bmps.py) -- so ln Z is undefined;
+    the cache is sound: no numeric failure is reported, the statistics flag
+    the estimate, and sampling gives finite log q."""
+    Js = [workloads.instance(64, "pmj", 9, 13)]
+    G.say("undefined ln Z estimate at chi 2")
+    run = G.Run(Js, 2, 1.5, tnmc.FP32, max_samples=8)
+    tnmc.tnmc_env_check(run.env)
+    st = run.stats()
+    assert not np.isfinite(run.logz[0])
+    assert st[0, tnmc.STAT_LOGZ_UNDEFINED] == 1 and st[0, tnmc.STAT_NONFINITE] == 0
+    _, lq, _ = run.sample(8, seed=5)
+    assert np.all(np.isfinite(lq))

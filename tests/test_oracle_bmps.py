@@ -98,3 +98,15 @@ def test_mattis_gauge_invariance_at_truncated_chi():
     _, _, a = bmps.build_cache(1.0, jh, jv, chi)
     _, _, b = bmps.build_cache(1.0, jh2, jv2, chi)
     assert abs(a - b) < 1e-11 * abs(a)
+
+
+def test_truncated_total_can_be_non_positive():
+    """At chi = 2 the truncated network is not a positive function: for this
+    +-J 64x64 instance at beta 1.5 its total (every spin of row 0 summed) is
+    not positive, so ln Z_TN is undefined (the GPU path reports the same,
+    test_gpu_parity.py)."""
+    import pytest
+    import workloads
+    jh, jv = workloads.instance(64, "pmj", 9, 13)
+    with pytest.raises(ValueError):
+        bmps.build_cache(1.5, jh, jv, 2)
