@@ -107,7 +107,17 @@ typedef struct tnmc_problem {
     const int64_t *off_h;   /* host [B] or NULL: element offset of instance i */
     const int64_t *off_v;   /*   in J_h / J_v; NULL = packed in batch order   */
     int32_t coupling_kind;  /* TNMC_COUPLING_*, declares the exact-energy mode */
+    int32_t flags;          /* 0 or TNMC_ALTERNATE_SWEEPS                      */
 } tnmc_problem;
+
+/* Problem flag: the compression of every second row (the rows L-3, L-5, ...
+ * counted from the bottom) runs mirrored -- QR sweep right to left, then the
+ * truncating SVD sweep left to right -- so that each row's sites are final
+ * in the order the next row's QR sweep consumes them.  Another canonical
+ * compression (section 2.2; the paper does not list its compress routine):
+ * identical in the exact regime, different at the level of the truncation
+ * error otherwise.  The cache is always stored in lattice order.           */
+#define TNMC_ALTERNATE_SWEEPS 1
 
 /* Per-instance Metropolis chain state (device memory, caller owned).
  * Zero-fill before the first tnmc_accept call of a chain.                */

@@ -132,6 +132,18 @@ def multiply(mpo, mps):
     return out
 
 
+def mirror(mps):
+    """The same state with the column order reversed: site c becomes site
+    L-1-c and its left and right bonds trade places."""
+    return [np.transpose(t, (2, 1, 0)).copy() for t in reversed(mps)]
+
+
+def row_is_mirrored(L: int, row: int, alternate: bool) -> bool:
+    """With alternating sweeps, the rows compressed second, fourth, ... from
+    the bottom (row L-3, L-5, ...) are compressed right to left."""
+    return alternate and (L - 2 - row) % 2 == 1
+
+
 def compress(mps, chi: int, diag=None):
     """QR sweep left->right, then truncating SVD sweep right->left.
 
@@ -172,13 +184,18 @@ def compress(mps, chi: int, diag=None):
     return logn, mps
 
 
-def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int, diag=None):
+def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int, diag=None, alternate: bool = False):
     """The full cache for one instance.
 
     Returns (cache, logscale, logZ) where cache[r] is the list of row r's
     site tensors (shapes (Dl, 2, Dr), normalised), logscale[r] the log of the
     norms taken out when row r was formed, and logZ the TN estimate of ln Z.
     `diag` (optional dict) collects the truncation conditioning, see compress.
+    With `alternate`, every second row (row_is_mirrored) is compressed in
+    the mirrored orientation -- QR sweep right to left, truncating SVD sweep
+    left to right -- an equally canonical compression (compress is not
+    listed in the paper) whose sites come out in the order the next row's
+    QR sweep consumes them.
     """
     J_h = np.asarray(J_h, dtype=np.float64)
     J_v = np.asarray(J_v, dtype=np.float64)
@@ -189,7 +206,11 @@ def build_cache(beta: float, J_h: np.ndarray, J_v: np.ndarray, chi: int, diag=No
     cache[L - 1] = mps
     for row in range(L - 2, -1, -1):
         mps = multiply(row_mpo(beta, J_h, J_v, row), mps)
-        logscale[row], mps = compress(mps, chi, diag)
+        if row_is_mirrored(L, row, alternate):
+            logscale[row], mps = compress(mirror(mps), chi, diag)
+            mps = mirror(mps)
+        else:
+            logscale[row], mps = compress(mps, chi, diag)
         cache[row] = mps
     return cache, logscale, float(logscale.sum() + log_total(cache[0]))
 

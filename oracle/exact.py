@@ -90,17 +90,22 @@ def _apply_site_matrices(psi, mats):
     return t.reshape(-1)
 
 
-def _truncate_dense(psi, L, chi):
-    """Sequential Schmidt truncation, bond (L-2|L-1) first, then leftwards."""
+def _truncate_dense(psi, L, chi, mirrored=False):
+    """Sequential Schmidt truncation, bond (L-2|L-1) first, then leftwards;
+    mirrored: bond (0|1) first, then rightwards."""
+    if mirrored:
+        psi = psi.reshape((2,) * L).transpose(tuple(range(L - 1, -1, -1))).reshape(-1)
     for c in range(L - 1, 0, -1):
         M = psi.reshape(2 ** c, 2 ** (L - c))
         U, S, Vt = np.linalg.svd(M, full_matrices=False)
         k = min(chi, S.shape[0])
         psi = ((U[:, :k] * S[:k]) @ Vt[:k]).reshape(-1)
+    if mirrored:
+        psi = psi.reshape((2,) * L).transpose(tuple(range(L - 1, -1, -1))).reshape(-1)
     return psi
 
 
-def transfer_vectors(J_h, J_v, beta, chi=None):
+def transfer_vectors(J_h, J_v, beta, chi=None, alternate=False):
     """Row vectors psi_r (normalised) and the log-scales taken out.
 
     psi_r(s) is proportional to sum over rows > r of exp(-beta E(rows >= r));
@@ -127,7 +132,8 @@ def transfer_vectors(J_h, J_v, beta, chi=None):
         n0 = np.linalg.norm(psi)
         psi = psi / n0
         if chi is not None:
-            psi = _truncate_dense(psi, L, chi)
+            # every second row mirrored, as the alternating compression does
+            psi = _truncate_dense(psi, L, chi, alternate and (L - 2 - r) % 2 == 1)
         n1 = np.linalg.norm(psi)
         psis[r], ls[r] = psi / n1, math.log(n0) + math.log(n1)
     logZ = float(ls.sum() + math.log(psis[0].sum()))

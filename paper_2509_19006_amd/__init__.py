@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so"
 
 TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP, TNMC_ENUMERIC = 0, -1, -2, -3, -4, -5
 COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20 = 0, 1, 2
+ALTERNATE_SWEEPS = 1
 FP64, FP32, MIXED_BF16, MIXED_FP16, MIXED_BF16X3 = 0, 1, 2, 3, 4
 SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16, "bf16x3": MIXED_BF16X3}
@@ -33,7 +34,8 @@ class TnmcError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("batch", c_int32), ("L", POINTER(c_int32)), ("chi", POINTER(c_int32)),
                 ("beta", POINTER(c_double)), ("J_h", c_void_p), ("J_v", c_void_p),
-                ("off_h", POINTER(c_int64)), ("off_v", POINTER(c_int64)), ("coupling_kind", c_int32)]
+                ("off_h", POINTER(c_int64)), ("off_v", POINTER(c_int64)), ("coupling_kind", c_int32),
+                ("flags", c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -134,10 +136,11 @@ class Problem:
 
     Either uniform: J_h (B, L, L-1), J_v (B, L-1, L) with scalar or per-instance
     chi/beta; or uneven: flat J_h / J_v with per-instance L and offsets.
-    coupling_kind is one of COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20.
+    coupling_kind is one of COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20;
+    flags 0 or ALTERNATE_SWEEPS.
     """
 
-    def __init__(self, J_h, J_v, L, chi, beta, off_h=None, off_v=None, coupling_kind=COUPLING_GENERAL):
+    def __init__(self, J_h, J_v, L, chi, beta, off_h=None, off_v=None, coupling_kind=COUPLING_GENERAL, flags=0):
         import numpy as np
         self.J_h, self.J_v = J_h, J_v
         B = len(L)
@@ -148,12 +151,14 @@ class Problem:
         self.off_v = None if off_v is None else np.ascontiguousarray(off_v, dtype=np.int64)
         self.batch = B
         self.coupling_kind = int(coupling_kind)
+        self.flags = int(flags)
         self._c = _Problem(
             B, self.L.ctypes.data_as(POINTER(c_int32)), self.chi.ctypes.data_as(POINTER(c_int32)),
             self.beta.ctypes.data_as(POINTER(c_double)),
             None if J_h is None else J_h.data_ptr(), None if J_v is None else J_v.data_ptr(),
             None if self.off_h is None else self.off_h.ctypes.data_as(POINTER(c_int64)),
-            None if self.off_v is None else self.off_v.ctypes.data_as(POINTER(c_int64)), self.coupling_kind)
+            None if self.off_v is None else self.off_v.ctypes.data_as(POINTER(c_int64)), self.coupling_kind,
+            self.flags)
 
     @classmethod
     def uniform(cls, J_h, J_v, chi, beta):

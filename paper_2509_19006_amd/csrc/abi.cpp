@@ -134,6 +134,7 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
     }
     if (p->coupling_kind < TNMC_COUPLING_GENERAL || p->coupling_kind > TNMC_COUPLING_GRID20)
         return fail(TNMC_EINVAL, "unknown coupling_kind");
+    if (p->flags & ~TNMC_ALTERNATE_SWEEPS) return fail(TNMC_EINVAL, "unknown problem flags");
     return TNMC_OK;
 }
 
@@ -173,7 +174,7 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
     for (int i = 0; i < B; ++i) {
         InstDesc &d = pl.desc[i];
         const int L = p->L[i], chi = p->chi[i];
-        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.pad0 = 0;
+        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = p->flags & TNMC_ALTERNATE_SWEEPS;
         d.beta = p->beta[i];
         d.off_h = p->off_h ? p->off_h[i] : oh;
         d.off_v = p->off_v ? p->off_v[i] : ov;

@@ -61,6 +61,7 @@ tnmc_problem replica_problem(const Replica &r, const tnmc_problem *p, const floa
     q.L = r.L.data(); q.chi = r.chi.data(); q.beta = r.beta.data();
     q.J_h = jh; q.J_v = jv; q.off_h = r.oh.data(); q.off_v = r.ov.data();
     q.coupling_kind = p->coupling_kind;
+    q.flags = p->flags;
     return q;
 }
 
@@ -180,6 +181,7 @@ size_t tnmc_autotune_workspace_bytes(const tnmc_problem *p, int32_t precision, i
         tnmc_problem s{};
         s.batch = (int32_t)L.size(); s.L = L.data(); s.chi = chi.data(); s.beta = beta.data();
         s.coupling_kind = p->coupling_kind;
+        s.flags = p->flags;
         split += align_up(tnmc_workspace_bytes(&s, precision, n_samples));
     }
     return layout(r, p->batch, n_samples, std::max(one, split)).total;
@@ -283,6 +285,7 @@ int tnmc_autotune(const tnmc_problem *p, int32_t precision, int32_t n_samples, i
                 q.batch = (int32_t)Ls[k].size(); q.L = Ls[k].data(); q.chi = chis[k].data(); q.beta = betas[k].data();
                 q.J_h = jh; q.J_v = jv; q.off_h = ohs[k].data(); q.off_v = ovs[k].data();
                 q.coupling_kind = p->coupling_kind;
+                q.flags = p->flags;
                 const size_t wb = align_up(tnmc_workspace_bytes(&q, precision, n));
                 hipStream_t s2;
                 if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) { rc = tnmc::set_error(TNMC_EHIP, "stream"); break; }

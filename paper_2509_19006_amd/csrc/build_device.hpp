@@ -872,13 +872,24 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 
     // write one parity-basis site (from a generator) to the ping-pong buffer
     // and its spin-basis form to the cache
+    // Row orientation.  With alternating sweeps (flag bit 0 of the
+    // descriptor) every second row is compressed mirrored: its "virtual"
+    // column v is the lattice column L-1-v and the left and right bonds of a
+    // site trade places; the QR sweep then runs right to left and the SVD
+    // sweep left to right on the lattice.  A row is kept in the ping-pong
+    // buffer in its own orientation; the cache is always written in lattice
+    // order.  The bottom row is not mirrored.
+    const bool alternate = (d.flags & 1) != 0;
+    auto mirrored = [&](int r) { return alternate && r <= L - 2 && ((L - 2 - r) & 1); };
     auto put_site = [&](int r, int c, int a, int b, T e0, T e1) {
+        const bool mr = mirrored(r);
         T *ps = prev + (size_t)(r & 1) * row_sz + (size_t)c * site_sz;
-        S *cs = cache + (size_t)r * row_sz + (size_t)c * site_sz;
+        S *cs = cache + (size_t)r * row_sz + (size_t)(mr ? L - 1 - c : c) * site_sz;
+        const int ce = mr ? b * chi + a : a * chi + b;
         ps[a * chi + b] = e0;
         ps[cc2 + a * chi + b] = e1;
-        cs[a * chi + b] = store_as<S, T>((e0 + e1) * RS2);
-        cs[cc2 + a * chi + b] = store_as<S, T>((e0 - e1) * RS2);
+        cs[ce] = store_as<S, T>((e0 + e1) * RS2);
+        cs[cc2 + ce] = store_as<S, T>((e0 - e1) * RS2);
     };
 
     // ---- bottom row (row L-1): every inner bond is (1 even, 1 odd) ---------
@@ -918,14 +929,18 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
 
     for (int r = L - 2; r >= 0; --r) {
         const T *orow = prev + (size_t)((r + 1) & 1) * row_sz;
+        // this row in its own orientation; the previous row read mirrored
+        // when the two orientations differ (old bond i of this row's view
+        // is the previous row's bond L - i, a site's bonds trade places)
+        const bool mir = mirrored(r), rd = mir != mirrored(r + 1);
 
         double part = 0.0;
         for (int c = tid; c < L; c += NT) {
-            const float v = jv[(size_t)r * L + c];
+            const float v = jv[(size_t)r * L + (mir ? L - 1 - c : c)];
             jrow[c] = v;
             part += beta * fabs((double)v);
             if (c < L - 1) {
-                const float h = jh[(size_t)r * (L - 1) + c];
+                const float h = jh[(size_t)r * (L - 1) + (mir ? L - 2 - c : c)];
                 jrow[L + c] = h;
                 part += beta * fabs((double)h);
             }
@@ -941,22 +956,23 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
         // site in place, all loads before the stores).
         constexpr int CPT = MAXB <= 32 ? MAXB * MAXB / NT : 1;
         T pre[CPT];
+        auto ob = [&](int i) { return rd ? L - i : i; };                    // old bond index
         auto fetch_site = [&](int cs) {
-            const int pa0 = dsec[2 * cs], Dp = pa0 + dsec[2 * cs + 1];
-            const int pb0 = dsec[2 * (cs + 1)], D = pb0 + dsec[2 * (cs + 1) + 1];
-            const T *os = orow + (size_t)cs * site_sz;
+            const int pa0 = dsec[2 * ob(cs)], Dp = pa0 + dsec[2 * ob(cs) + 1];
+            const int pb0 = dsec[2 * ob(cs + 1)], D = pb0 + dsec[2 * ob(cs + 1) + 1];
+            const T *os = orow + (size_t)(rd ? L - 1 - cs : cs) * site_sz;
 #pragma unroll
             for (int i = 0; i < CPT; ++i) {
                 const int e = tid + i * NT;
                 const int a = e >> LB, b = e & MM;
                 const int n = (a >= pa0) ^ (b >= pb0);
-                pre[i] = (a < Dp && b < D) ? os[n * cc2 + a * chi + b] : (T)0;
+                pre[i] = (a < Dp && b < D) ? os[n * cc2 + (rd ? b * chi + a : a * chi + b)] : (T)0;
             }
         };
         if constexpr (MAXB <= 32) fetch_site(0);
         for (int c = 0; c < L; ++c) {
-            const int pa0 = dsec[2 * c], Dp = pa0 + dsec[2 * c + 1];             // old left bond
-            const int pb0 = dsec[2 * (c + 1)], D = pb0 + dsec[2 * (c + 1) + 1];  // old right bond
+            const int pa0 = dsec[2 * ob(c)], Dp = pa0 + dsec[2 * ob(c) + 1];             // old left bond
+            const int pb0 = dsec[2 * ob(c + 1)], D = pb0 + dsec[2 * ob(c + 1) + 1];      // old right bond
             const int m0 = mq[2 * c], m1 = mq[2 * c + 1];
             const int K = m0 + m1;
             double lv0, lv1;
@@ -974,7 +990,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 }
                 if (c + 1 < L) fetch_site(c + 1);
             } else {
-                const T *os = orow + (size_t)c * site_sz;
+                const T *os = orow + (size_t)(rd ? L - 1 - c : c) * site_sz;
                 constexpr int CPW = MAXB * MAXB / NT;
                 T v[CPW];
 #pragma unroll
@@ -982,7 +998,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                     const int e = tid + i * NT;
                     const int a = e >> LB, b = e & MM;
                     const int n = (a >= pa0) ^ (b >= pb0);
-                    v[i] = (a < Dp && b < D) ? os[n * cc2 + a * chi + b] : (T)0;
+                    v[i] = (a < Dp && b < D) ? os[n * cc2 + (rd ? b * chi + a : a * chi + b)] : (T)0;
                 }
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {

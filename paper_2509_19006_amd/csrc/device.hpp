@@ -10,7 +10,7 @@ namespace tnmc {
 
 // Per-instance record kept in the workspace (device copy of the problem).
 struct InstDesc {
-    int32_t L, chi, W, pad0;
+    int32_t L, chi, W, flags;     // flags: TNMC_ALTERNATE_SWEEPS
     double beta;
     int64_t off_h, off_v;     // element offsets into J_h / J_v
     int64_t cache_off;        // byte offset of the cache [L][L][2][chi][chi]

@@ -297,3 +297,41 @@ def test_undefined_logz_estimate_is_not_a_cache_failure(G, tnmc):
     assert st[0, tnmc.STAT_LOGZ_UNDEFINED] == 1 and st[0, tnmc.STAT_NONFINITE] == 0
     _, lq, _ = run.sample(8, seed=5)
     assert np.all(np.isfinite(lq))
+
+
+ALT_CASES = [
+    # (name, L list, family, chi, beta, precision)
+    ("4x4 exact", [4, 4], "gauss", 4, 1.5, 0),
+    ("12x12 chi4", [12, 13], "gauss", 4, 1.0, 0),
+    ("16x16 chi32", [16, 16], "pmj", 32, 1.0, 0),
+    ("uneven L", [2, 3, 9, 17], "pmj", 8, 0.7, 0),
+    ("20x20 chi16 fp32", [20, 21], "gauss", 16, 1.0, 1),
+    ("20x20 chi40 fp32", [20, 20], "pmj", 40, 1.0, 1),
+]
+
+
+@pytest.mark.parametrize("case", ALT_CASES, ids=[c[0] for c in ALT_CASES])
+def test_alternating_sweeps_match_the_oracle(G, tnmc, case):
+    """With TNMC_ALTERNATE_SWEEPS every second row is compressed mirrored;
+    ln Z and the teacher-forced log q of oracle draws equal the oracle's
+    alternating compression (mirrored rows read the previous row reversed
+    and write the cache back in lattice order)."""
+    name, Ls, fam, chi, beta, prec = case
+    Js = [workloads.instance(L, fam, 46, i) for i, L in enumerate(Ls)]
+    G.say(f"alternating sweeps {name}: L={Ls} chi={chi} prec={prec}")
+    run = G.Run(Js, chi, beta, prec, max_samples=32, flags=tnmc.ALTERNATE_SWEEPS)
+    tol = TOL[prec]
+    k = 12
+    forced, want = [], []
+    for i, (jh, jv) in enumerate(Js):
+        dg = {}
+        cache, _, lz = bmps.build_cache(beta, jh, jv, chi, dg, alternate=True)
+        print(f"  instance {i}: ln Z {run.logz[i]:.12f} vs {lz:.12f}, cut conditioning {dg.get('cond', 0):.1e}")
+        assert rel_err(run.logz[i], lz) < tol
+        bits, olq, _ = sampler.sample(cache, beta, jv, k, seed=46, instance=i)
+        forced.append(2 * bits - 1)
+        want.append(olq)
+    _, lq, _ = run.sample(k, forced=forced)
+    for i in range(len(Js)):
+        print(f"  instance {i}: max relative log q error {np.max(rel_err(lq[i], want[i])):.2e}")
+        assert np.max(rel_err(lq[i], want[i])) < tol

@@ -33,13 +33,15 @@ def test_below_exact_chi_is_not_exact():
     assert abs(lz4 - tz) > 1e-8
 
 
+@pytest.mark.parametrize("alternate", [False, True])
 @pytest.mark.parametrize("L,chi", [(6, 2), (6, 3), (8, 3), (8, 5)])
-def test_truncated_equals_dense_sequential_truncation(L, chi):
+def test_truncated_equals_dense_sequential_truncation(L, chi, alternate):
     """At truncated chi, every cached row equals the dense row vector with
-    the same right-to-left Schmidt truncation, and ln Z agrees."""
+    the same Schmidt truncation (right-to-left; with alternating sweeps every
+    second row left-to-right), and ln Z agrees."""
     jh, jv = workloads.instance(L, "pmj", 13, L + chi)
-    cache, ls, lz = bmps.build_cache(1.0, jh, jv, chi)
-    psis, tls, tz = exact.transfer_vectors(jh, jv, 1.0, chi=chi)
+    cache, ls, lz = bmps.build_cache(1.0, jh, jv, chi, alternate=alternate)
+    psis, tls, tz = exact.transfer_vectors(jh, jv, 1.0, chi=chi, alternate=alternate)
     assert abs(lz - tz) < 1e-10 * abs(tz)
     for r in range(L):
         v = bmps.mps_to_dense(cache[r])
@@ -110,3 +112,27 @@ def test_truncated_total_can_be_non_positive():
     jh, jv = workloads.instance(64, "pmj", 9, 13)
     with pytest.raises(ValueError):
         bmps.build_cache(1.5, jh, jv, 2)
+
+
+def test_alternating_sweeps_change_only_the_truncation():
+    """The mirrored compression is another canonical truncation: in the
+    exact regime both orders give the same ln Z to rounding; truncated, they
+    differ (at the truncation error) -- so oracle and kernel must agree on
+    the order."""
+    jh, jv = workloads.instance(8, "gauss", 14, 0)
+    _, _, a = bmps.build_cache(1.0, jh, jv, 16)
+    _, _, b = bmps.build_cache(1.0, jh, jv, 16, alternate=True)
+    assert abs(a - b) < 1e-12 * abs(a)
+    _, _, a = bmps.build_cache(1.0, jh, jv, 2)
+    _, _, b = bmps.build_cache(1.0, jh, jv, 2, alternate=True)
+    assert abs(a - b) > 1e-9 * abs(a)
+
+
+def test_mirror_is_an_involution_and_keeps_the_state():
+    jh, jv = workloads.instance(6, "pmj", 15, 0)
+    mps, _ = bmps.bottom_row_mps(1.0, jh)
+    v = bmps.mps_to_dense(mps).reshape((2,) * 6)
+    w = bmps.mps_to_dense(bmps.mirror(mps)).reshape((2,) * 6)
+    assert np.allclose(w, v.transpose(5, 4, 3, 2, 1, 0))
+    back = bmps.mirror(bmps.mirror(mps))
+    assert all(np.array_equal(x, y) for x, y in zip(back, mps))

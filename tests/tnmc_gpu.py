@@ -53,12 +53,12 @@ def unpack(words, Ls, n):
 class Run:
     """A batch of instances built on the GPU at one precision."""
 
-    def __init__(self, Js, chi, beta, precision, max_samples=256):
+    def __init__(self, Js, chi, beta, precision, max_samples=256, flags=0):
         self.Ls = [int(jh.shape[0]) for jh, _ in Js]
         self.B = len(Js)
         self.jh = torch.as_tensor(np.concatenate([np.asarray(jh, np.float32).ravel() for jh, _ in Js])).cuda()
         self.jv = torch.as_tensor(np.concatenate([np.asarray(jv, np.float32).ravel() for _, jv in Js])).cuda()
-        self.problem = T.Problem(self.jh, self.jv, self.Ls, chi, beta)
+        self.problem = T.Problem(self.jh, self.jv, self.Ls, chi, beta, flags=flags)
         self.precision = precision
         nbytes = T.tnmc_workspace_size(self.problem, precision, max_samples)
         self.ws = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
