@@ -35,31 +35,43 @@ METRIC = "accepted samples/s at L=256 chi=32 + acceptance rate, learned/mixed vs
 # MFMA flop/s, HBM bytes/s
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "mfma16": 2.5e15, "hbm": 8.0e12}
 
-# HBM traffic of one cache-build launch at the default workload, from two
-# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
-# read for a plain copy of known size; valid only for the kernel source it
-# was measured on (sha256 over the files below), reported as null otherwise.
-TRAFFIC_SOURCES = ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
-                   "paper_2509_19006_amd/csrc/device.hpp"]
-TRAFFIC = {"sha256": "e934049df3328d5f7e2e9a1202f3601e92499ed3f98c4e996ba97a901a385582",
-           "bytes": 870260078330,
-           "profile": "profiles/k_build_k_sample_c3_fp16_hbm_traffic.txt"}
+# HBM bytes per launch at the default workload (256 x 256, chi 32, 256 x 256)
+# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by
+# what the same counter reads for a plain device copy of known size; valid
+# only for the kernel source they were measured on (sha256 over the files
+# listed), reported as null otherwise.
+TRAFFIC_PROFILE = "profiles/k_build_k_sample_mfma_256x256_chi32_hbm_traffic.txt"
+TRAFFIC = {
+    "k_build": {"sources": ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
+                            "paper_2509_19006_amd/csrc/device.hpp"],
+                "sha256": "ba5579ad6342450d02df08bf1f304af31e9372ca79ed375139f599c0af2d53e0",
+                "bytes": {"fp32": 939003884802, "bf16x3": 939003884802,
+                          "fp16": 870267542202}},
+    "k_sample_mfma": {"sources": ["paper_2509_19006_amd/csrc/sample.hip", "paper_2509_19006_amd/csrc/sample_mfma.hpp",
+                                  "paper_2509_19006_amd/csrc/device.hpp"],
+                      "sha256": "06f9a640028de95975a2c771abf3075942ce2921f4bb7bc87d8754a321b87571",
+                      "bytes": {"fp32": 1388337726130, "bf16x3": 1388221583791,
+                                "fp16": 1250828227911}},
+}
+
+
+def traffic_for(kernel, form):
+    """Counter-measured HBM bytes of one launch of kernel in the given form,
+    or None when the kernel's source has changed since the measurement."""
+    import hashlib
+    ent = TRAFFIC.get(kernel)
+    if ent is None or form not in ent["bytes"]:
+        return None
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for f in ent["sources"]:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return ent["bytes"][form] if h.hexdigest() == ent["sha256"] else None
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def traffic_for_current_kernel():
-    import hashlib
-    if TRAFFIC is None:
-        return None
-    h = hashlib.sha256()
-    here = os.path.dirname(os.path.abspath(__file__))
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(here, f), "rb") as fh:
-            h.update(fh.read())
-    return TRAFFIC["bytes"] if h.hexdigest() == TRAFFIC["sha256"] else None
 
 
 def build_flops_dense(L, chi, B):
@@ -152,11 +164,23 @@ def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed):
                wall_s=wall, ms_per_step=1e3 * wall / steps,
                build_ms=phase[0], sample_ms=phase[1], energy_ms=phase[2], accept_ms=phase[3],
                jacobi_sweeps_per_site=float(stats[:, 0].mean()) / ((L - 1) * L),
+               build_phase_share=build_phase_share(stats),
                mean_energy_per_spin=float(E.mean().item()) / (L * L),
                logz_mean=float(logz.mean().item()))
     del envs, ws
     torch.cuda.empty_cache()
     return out
+
+
+def build_phase_share(stats):
+    """Shares of an instance's build time (device wall clock, averaged over
+    instances) spent in the QR sweep (of it, the Householder
+    factorisations) and in the SVD sweep (of it, the Jacobi)."""
+    import numpy as np
+    st = np.asarray(stats, dtype=np.float64)
+    tot = np.maximum(st[:, 5] - st[:, 4], 1.0)
+    share = lambda i: round(float((st[:, i] / tot).mean()), 4)
+    return {"qr_sweep": share(1), "householder": share(7), "svd_sweep": share(2), "jacobi": share(3)}
 
 
 def cpu_model():
@@ -170,11 +194,19 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline_child(L, chi, beta, n_sample):
-    """The oracle end to end on one instance of the workload (the first
-    disorder of the batch): the float64 cache build of all L - 1 rows,
-    n_sample draws, their energies and the Metropolis chain over them.
-    Prints one JSON line; runs in a child process beside the GPU forms."""
+# the oracle leg runs on a smaller lattice of the same family (same chi,
+# beta and coupling distribution) so that it stays at a few tens of seconds
+# of host work; its rate is scaled to the workload's side by the number of
+# site-rows, which sets the cost of both the cache build and a draw
+CPU_SAMPLE_L = 128
+
+
+def cpu_baseline_child(L, chi, beta, n_sample, L_full):
+    """The oracle end to end on one instance (the first disorder of a batch
+    of side L): the float64 cache build of all L - 1 rows, n_sample draws,
+    their energies and the Metropolis chain over them.  Prints progress to
+    stderr and one JSON line to stdout; runs in a child process beside the
+    GPU forms."""
     import numpy as np
     import workloads
     from oracle import bmps, ising, mis, sampler
@@ -188,19 +220,26 @@ def cpu_baseline_child(L, chi, beta, n_sample):
     t0 = time.perf_counter()
     cache, _, _ = bmps.build_cache(beta, jh, jv, chi)
     t_build = time.perf_counter() - t0
+    log(f"  oracle leg: cache build of {L - 1} rows done ({t_build:.1f} s)")
     bits, logq, _ = sampler.sample(cache, beta, jv, n_sample, seed=0x5A5A0003)
     E = ising.energy(2 * bits - 1, jh, jv)
     chain = mis.Chain()
     mis.accept(logq, E, beta, chain, 0x5A5A0003, 0, 0)
     wall = time.perf_counter() - t0
-    print(json.dumps({"value": chain.n_acc / wall, "unit": "accepted samples/s", "cores": int(cores),
+    log(f"  oracle leg: {n_sample} draws and the chain done ({wall:.1f} s)")
+    rate = chain.n_acc / wall
+    scale = (L * (L - 1)) / (L_full * (L_full - 1))
+    print(json.dumps({"value": rate * scale, "unit": "accepted samples/s", "cores": int(cores),
                       "kind": "oracle", "cpu": cpu_model(),
+                      "value_at_sample_size": rate, "scale_to_workload": scale,
                       "acceptance": chain.n_acc / max(1, chain.n_trials), "trials": chain.n_trials,
                       "wall_s": wall, "build_s": t_build,
-                      "sample": (f"one {L}x{L} +-J instance of the workload (chi={chi}, beta={beta}): the "
-                                 f"float64 cache build of all {L - 1} rows ({t_build:.1f} s), {n_sample} "
+                      "sample": (f"one {L}x{L} +-J instance of the workload's family (chi={chi}, beta={beta}): "
+                                 f"the float64 cache build of all {L - 1} rows ({t_build:.1f} s), {n_sample} "
                                  f"draws, their energies and the oracle's own Metropolis chain "
-                                 f"({chain.n_acc} of {chain.n_trials} trials accepted), timed end to end")}),
+                                 f"({chain.n_acc} of {chain.n_trials} trials accepted), timed end to end; "
+                                 f"the rate scaled to {L_full}x{L_full} by the site-row ratio "
+                                 f"{L}*{L - 1}/({L_full}*{L_full - 1})")}),
           flush=True)
 
 
@@ -208,13 +247,22 @@ def start_cpu_baseline(L, chi, beta, n_sample=8):
     """Starts the oracle leg as a child process before this process touches
     the GPU; collect it with finish_cpu_baseline."""
     import subprocess
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--L", str(L), "--chi", str(chi),
-           "--beta", str(beta), "--samples", str(n_sample)]
+    Ls = min(L, CPU_SAMPLE_L)
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--L", str(Ls), "--chi", str(chi),
+           "--beta", str(beta), "--samples", str(n_sample), "--full-L", str(L)]
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)
 
 
-def finish_cpu_baseline(proc):
-    out, _ = proc.communicate()
+def finish_cpu_baseline(proc, timeout_s=240):
+    import subprocess
+    log("waiting for the oracle leg")
+    try:
+        out, _ = proc.communicate(timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        proc.communicate()
+        log(f"oracle leg still running after {timeout_s} s more: stopped, no cpu baseline")
+        return None
     if proc.returncode != 0:
         log(f"cpu baseline failed with status {proc.returncode}")
         return None
@@ -567,6 +615,7 @@ def main():
                     help="precision forms of the headline workload, comma separated (the first is fp32): "
                          "fp32, bf16x3, fp16, bf16")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--full-L", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["headline", "uneven", "learned", "paper", "sweep", "rbim"],
                     default="headline",
@@ -587,7 +636,7 @@ def main():
         if getattr(args, k) is None:
             setattr(args, k, v)
     if args.cpu_baseline_child:
-        cpu_baseline_child(args.L, args.chi, args.beta, args.samples)
+        cpu_baseline_child(args.L, args.chi, args.beta, args.samples, args.full_L or args.L)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the instances are independent and this build runs "
@@ -644,6 +693,7 @@ def main():
     plain = forms["fp32"]
 
     # the dominant kernel: the cache build (float32 vector ALU, latency bound)
+    default_size = (L, chi, B, N) == (256, 32, 256, 256)
     S = plain["jacobi_sweeps_per_site"]
     ex = build_flops_executed(L, chi, B, S)
     dense = build_flops_dense(L, chi, B)
@@ -651,7 +701,8 @@ def main():
     roof = {"bound": "alu", "kernel": "k_build (cache build, float32 arithmetic)",
             "achieved": ex / t_build / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
             "frac": ex / t_build / PEAK["fp32"],
-            "traffic": traffic_for_current_kernel() if (L, chi, B) == (256, 32, 256) else None,
+            "traffic": traffic_for("k_build", "fp32") if default_size else None,
+            "traffic_profile": TRAFFIC_PROFILE,
             "flops_per_launch": ex,
             "per_unit": (f"(2 chi^2 +) (25.3 + 14 S) chi^3 flop per site-row executed by the parity-block "
                          f"kernel, S = {S:.2f} measured Jacobi sweeps per site"),
@@ -679,7 +730,7 @@ def main():
             "frac": (by / t / PEAK["hbm"]) if bound_hbm else (fl / t / peak),
             "flops_per_launch": fl, "algorithmic_bytes": by, "intensity_flop_per_byte": fl / by,
             "hbm_frac_of_algorithmic_bytes": by / t / PEAK["hbm"],
-            "peak_kind": pname, "traffic": None}
+            "peak_kind": pname, "traffic": traffic_for("k_sample_mfma", name) if default_size else None}
 
     cpu = finish_cpu_baseline(cpu_proc) if cpu_proc is not None else None
 
