@@ -198,7 +198,7 @@ def cpu_model():
 # beta and coupling distribution) so that it stays at a few tens of seconds
 # of host work; its rate is scaled to the workload's side by the number of
 # site-rows, which sets the cost of both the cache build and a draw
-CPU_SAMPLE_L = 128
+CPU_SAMPLE_L = 96
 
 
 def cpu_baseline_child(L, chi, beta, n_sample, L_full):

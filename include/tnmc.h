@@ -61,7 +61,11 @@ extern "C" {
 
 /* ---- precision of the boundary-MPS build and of the sampler ----------- */
 /* Every form keeps log-scales, ln Z, log q, p(+1), the Metropolis log-ratio
- * and the accept decision in float64.  In the float forms the sampler's two
+ * and the accept decision in float64.  In the float builds a truncation
+ * whose float32 one-sided Jacobi does not reach orthogonality (its columns'
+ * relative inner products below 2 eps sqrt(K)) within 40 sweeps is redone
+ * in float64 from the same float32 inputs (slot 11 of tnmc_env_stats counts
+ * these).  In the float forms the sampler's two
  * contractions per site run on the matrix cores for chi <= 32 (the sample
  * vectors are float32 and enter 16-bit products as hi + lo pairs) and on the
  * vector unit in float32 for chi > 32.                                    */
@@ -107,7 +111,7 @@ typedef struct tnmc_problem {
     const int64_t *off_h;   /* host [B] or NULL: element offset of instance i */
     const int64_t *off_v;   /*   in J_h / J_v; NULL = packed in batch order   */
     int32_t coupling_kind;  /* TNMC_COUPLING_*, declares the exact-energy mode */
-    int32_t flags;          /* 0 or TNMC_ALTERNATE_SWEEPS                      */
+    int32_t flags;          /* 0 or TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK */
 } tnmc_problem;
 
 /* Problem flag: the compression of every second row (the rows L-3, L-5, ...
@@ -118,6 +122,12 @@ typedef struct tnmc_problem {
  * identical in the exact regime, different at the level of the truncation
  * error otherwise.  The cache is always stored in lattice order.           */
 #define TNMC_ALTERNATE_SWEEPS 1
+
+/* Problem flag for the float builds: stop the float32 Jacobi after one
+ * sweep, so that every truncation still rotating after it takes the
+ * float64 redo (an exercise of that path: the build slows down, results
+ * stay within the float forms' tolerance).  No effect on TNMC_FP64.       */
+#define TNMC_FORCE_F64_FALLBACK 2
 
 /* Per-instance Metropolis chain state (device memory, caller owned).
  * Zero-fill before the first tnmc_accept call of a chain.                */
@@ -393,7 +403,10 @@ int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
  * Householder factorisations (a part of the QR sweeps); the number of
  * truncations whose Jacobi reached the sweep limit; the number of row
  * log-scales that are not finite; 1 if ln Z is undefined (the truncated
- * network's total was not positive); slots 11-15 are zero.  The
+ * network's total was not positive); the number of truncations whose
+ * float32 Jacobi did not converge and were redone in float64 (float builds;
+ * slot 8 then counts the float64 Jacobi reaching its limit); slots 12-15
+ * are zero.  The
  * build processes instances in decreasing order of estimated cost
  * (L-1) L chi^3.
  * NULL for a NULL env.                                                    */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so"
 TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP, TNMC_ENUMERIC = 0, -1, -2, -3, -4, -5
 COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20 = 0, 1, 2
 ALTERNATE_SWEEPS = 1
+FORCE_F64_FALLBACK = 2
 FP64, FP32, MIXED_BF16, MIXED_FP16, MIXED_BF16X3 = 0, 1, 2, 3, 4
 SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16, "bf16x3": MIXED_BF16X3}
@@ -137,7 +138,7 @@ class Problem:
     Either uniform: J_h (B, L, L-1), J_v (B, L-1, L) with scalar or per-instance
     chi/beta; or uneven: flat J_h / J_v with per-instance L and offsets.
     coupling_kind is one of COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20;
-    flags 0 or ALTERNATE_SWEEPS.
+    flags 0, ALTERNATE_SWEEPS and/or FORCE_F64_FALLBACK.
     """
 
     def __init__(self, J_h, J_v, L, chi, beta, off_h=None, off_v=None, coupling_kind=COUPLING_GENERAL, flags=0):
@@ -295,7 +296,7 @@ def tnmc_philox_uniform(seed: int, c0, c1: int, c2: int, stream_id: int, out, st
 
 
 STATS_PER_INST = 16
-STAT_MAXSWEEP, STAT_NONFINITE, STAT_LOGZ_UNDEFINED = 8, 9, 10
+STAT_MAXSWEEP, STAT_NONFINITE, STAT_LOGZ_UNDEFINED, STAT_FALLBACK = 8, 9, 10, 11
 
 
 def tnmc_env_stats(env: Env):

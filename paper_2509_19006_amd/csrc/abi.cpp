@@ -134,7 +134,7 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
     }
     if (p->coupling_kind < TNMC_COUPLING_GENERAL || p->coupling_kind > TNMC_COUPLING_GRID20)
         return fail(TNMC_EINVAL, "unknown coupling_kind");
-    if (p->flags & ~TNMC_ALTERNATE_SWEEPS) return fail(TNMC_EINVAL, "unknown problem flags");
+    if (p->flags & ~(TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK)) return fail(TNMC_EINVAL, "unknown problem flags");
     return TNMC_OK;
 }
 
@@ -174,7 +174,7 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
     for (int i = 0; i < B; ++i) {
         InstDesc &d = pl.desc[i];
         const int L = p->L[i], chi = p->chi[i];
-        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = p->flags & TNMC_ALTERNATE_SWEEPS;
+        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = p->flags & (TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK);
         d.beta = p->beta[i];
         d.off_h = p->off_h ? p->off_h[i] : oh;
         d.off_v = p->off_v ? p->off_v[i] : ov;
@@ -188,8 +188,9 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
         off = align_up(off + sizeof(double) * L);
         d.cache_off = off;
         off = align_up(off + (size_t)L * L * 2 * chi * chi * ss);
-        d.qscr_off = off;
-        off = align_up(off + (size_t)L * 2 * 2 * chi * chi * ts);
+        d.qscr_off = off;      // Q slots, then (float builds) the float64 redo area
+        off = align_up(off + (size_t)L * 2 * 2 * chi * chi * ts +
+                       (ts == sizeof(float) ? sizeof(double) * tnmc::fallback_doubles(chi) : 0));
         d.prev_off = off;      // previous row in the parity basis (build arithmetic type)
         off = align_up(off + (size_t)2 * L * 2 * chi * chi * ts);
     }

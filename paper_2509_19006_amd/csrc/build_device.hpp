@@ -238,14 +238,19 @@ template <bool IL, typename T> __device__ __forceinline__ T from_prev(T v, int d
 // pivoting, which shortens cyclic Jacobi).  On return the rotated block is back at Tb and W (n x n, same
 // leading dimension) at Wb, and the block wave writes the singular values
 // (column norms) of the positions to nrm_out[0, n): -1 for positions >= kr
-// and for an empty block.  Returns the sweep count (role 0).
-template <typename T, int CHI, bool IL>
-__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *nrm_out, int kr) {
+// and for an empty block.  Returns the sweep count (role 0); a count equal to
+// max_sweeps means the last sweep still rotated (not converged).  The block
+// and W sit in shared memory (LDSP) or in global memory.
+template <typename T, int CHI, bool IL, bool LDSP = true>
+__device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, T *nrm_out, int kr,
+                          int max_sweeps) {
     static_assert(!IL || CHI == 32, "the interleaved layout rotates 16-lane rows");
     constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
     if (role != 0) return 0;
+    // the block in shared memory (LDSP) or in global memory
     typedef __attribute__((address_space(3))) T LT;
-    LT *Tl = (LT *)Tb, *Wl = (LT *)Wb;
+    typedef typename std::conditional<LDSP, LT, T>::type PT;
+    PT *Tl = (PT *)Tb, *Wl = (PT *)Wb;
     int g = IL ? (lane & 15) : lane / G, gl = IL ? (lane >> 4) : lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
     // pivoting: lane l < CHI measures column l, ranks it among all, and
@@ -257,7 +262,7 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
         T nl = (T)-1;
         if (lane < n) {
             T q0 = 0, q1 = 0;
-            const LT *cp = Tl + lane * ld;
+            const PT *cp = Tl + lane * ld;
             T q2 = 0, q3 = 0;
             int k = 0;
             for (; k + 3 < K; k += 4) {
@@ -298,7 +303,7 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
         const T tol = (T)2 * Eps<T>::v * sqrt((T)K);
         const T tol2 = tol * tol;
         T small = 0;
-        for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
+        for (int sw = 0; sw < max_sweeps; ++sw) {
             T a = 0, b = 0;
 #pragma unroll
             for (int i = 0; i < RK; ++i) { a += x[i] * x[i]; b += y[i] * y[i]; }
@@ -410,9 +415,10 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
 // until neither rotates (extra sweeps of a converged block rotate nothing).
 // prm: [2 blocks][2 slots][CHI/2][2], flags: [2].  On return the rotated
 // block is back at Tb (role 0) and W (n x n, same leading dimension) at Wb
-// (role 1).  Returns the sweep count.
+// (role 1).  Returns the sweep count (max_sweeps: not converged).
 template <typename T, int CHI>
-__device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, int p, T *prm, int *flags) {
+__device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int role, int p, T *prm, int *flags,
+                            int max_sweeps) {
     constexpr int HP = CHI / 2, G = 64 / HP, RK = CHI / G;
     int g = lane / G, gl = lane % G;
     asm volatile("" : "+v"(g), "+v"(gl));   // see qr_site
@@ -436,7 +442,7 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
     T *pp = prm + p * 4 * HP;
     T small = 0;
     int sweeps = 0, slot = 0;
-    for (int sw = 0; sw < MAX_SWEEPS; ++sw) {
+    for (int sw = 0; sw < max_sweeps; ++sw) {
         T a = 0, b = 0;
         if (blk) {
 #pragma unroll
@@ -521,16 +527,16 @@ __device__ int jacobi_split(T *Tb, T *Wb, int ld, int K, int n, int lane, int ro
 // and 3 carry their rotations W (role 1, through prm and flags), for
 // chi <= 32 the block's wave carries W itself.  For chi <= 32 the block
 // waves also write the singular values to nrm_out (see jacobi_reg).
-template <typename T, int MAXB>
+template <typename T, int MAXB, bool LDSP = true>
 __device__ int jacobi_block(T *Tb, T *Wb, int ld, int K, int n, int chi, int lane, int role, int p, T *prm,
-                            int *flags, T *nrm_out, int kr) {
+                            int *flags, T *nrm_out, int kr, int max_sweeps) {
     if constexpr (MAXB >= 64) {
-        if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags);
+        if (chi > 32) return jacobi_split<T, 64>(Tb, Wb, ld, K, n, lane, role, p, prm, flags, max_sweeps);
     }
     // chi <= 16: contiguous groups; chi <= 32: interleaved groups; W in the
     // block's wave
-    if (chi <= 16) return jacobi_reg<T, 16, false>(Tb, Wb, ld, K, n, lane, role, nrm_out, kr);
-    return jacobi_reg<T, 32, true>(Tb, Wb, ld, K, n, lane, role, nrm_out, kr);
+    if (chi <= 16) return jacobi_reg<T, 16, false, LDSP>(Tb, Wb, ld, K, n, lane, role, nrm_out, kr, max_sweeps);
+    return jacobi_reg<T, 32, true, LDSP>(Tb, Wb, ld, K, n, lane, role, nrm_out, kr, max_sweeps);
 }
 
 // Sum over a lane's rows of a[r] * b[r] in four independent partial sums
@@ -808,6 +814,65 @@ __device__ __forceinline__ void lam_of(double beta, float J, double &l0, double 
     l1 = (J >= 0.0f) ? d : -d;
 }
 
+// Float64 redo of one site's truncation in a float build whose float32
+// Jacobi did not converge on a block: the centres T^p = [Q^p_0 X^p,
+// Q^(1-p)_1 X^(1-p)] are formed again in float64 from the same float32 Q
+// slot q and carried X, both blocks go through the float64 Jacobi (the same
+// routine, block and rotations in the global area fb, see
+// fallback_doubles), and the rotated blocks, W and the singular values come
+// back into the float32 arrays the truncation step reads (Tm, Wm: [2][bst],
+// column-major, leading dimension ldt; nrm: [2][n]).  Called by all threads
+// of the workgroup; the two blocks' float64 sweep counts go to iflag.
+template <int MAXB>
+__device__ void svd_redo_f64(double *fb, const float *q, const float *X, float *Tm, float *Wm, float *nrm,
+                             int *iflag, int *jflag, int c, int L, int chi, int K0, int K1, int r0, int r1,
+                             int mn0, int mn1, int n, int kr, int ldt, int bst) {
+    const int tid = threadIdx.x, cc2 = chi * chi;
+    double *Td = fb, *Wd = fb + 2 * bst, *prm = fb + 4 * bst, *nd = prm + 256;
+    for (int e = tid; e < 2 * n * ldt; e += NT) Td[(e / (n * ldt)) * bst + e % (n * ldt)] = 0.0;
+    __syncthreads();
+    if (c == L - 1) {
+        // the sweep's first centre: one column, rows of both QR sectors
+        for (int e = tid; e < K0 + K1; e += NT) {
+            const int p = e >= K0, k = p ? e - K0 : e;
+            Td[p * bst + k] = (double)q[e];
+        }
+    } else {
+        for (int e = tid; e < 2 * n * chi; e += NT) {
+            const int p = e / (n * chi), k = (e / n) % chi, idx = e % n;
+            const int Kp = p ? K1 : K0;
+            if (k >= Kp || idx >= kr) continue;
+            // column idx < d^p: (s = 0, m = idx) from Q^p's sigma = 0 rows;
+            // else (s = 1) from Q^(1-p)'s sigma = 1 rows
+            const int dp = p ? r1 : r0;
+            const bool s1 = idx >= dp;
+            const int qb = s1 ? 1 - p : p, xc = s1 ? idx - dp : idx;
+            const int rowoff = s1 ? (qb == 0 ? K0 : K1) : 0;
+            const int mcq = qb ? mn1 : mn0;
+            const float *qr = q + qb * 2 * cc2 + (rowoff + k) * chi;
+            const float *xr = X + qb * cc2 + xc;
+            double acc = 0.0;
+            for (int j = 0; j < mcq; ++j) acc += (double)qr[j] * (double)xr[j * chi];
+            Td[p * bst + idx * ldt + k] = acc;
+        }
+    }
+    __syncthreads();
+    const int wv = tid >> 6, pb = wv & 1;
+    const int sw = jacobi_block<double, MAXB, false>(Td + pb * bst, Wd + pb * bst, ldt, pb ? K1 : K0, n, chi,
+                                                     tid & 63, wv >> 1, pb, prm, jflag, nd + pb * n, kr,
+                                                     MAX_SWEEPS);
+    if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
+    __syncthreads();
+    for (int e = tid; e < 2 * n * ldt; e += NT) {
+        const int p = e / (n * ldt), col = (e / ldt) % n, k = e % ldt;
+        const int at = p * bst + col * ldt + k;
+        Tm[at] = (float)Td[at];
+        if (k < n) Wm[at] = (float)Wd[at];
+    }
+    for (int e = tid; e < 2 * n; e += NT) nrm[e] = (float)nd[e];
+    __syncthreads();
+}
+
 template <typename T, typename S, int MAXB>
 __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                                const float *__restrict__ Jh_all, const float *__restrict__ Jv_all,
@@ -867,7 +932,11 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
     // the current row's couplings (vertical, then horizontal)
     float *jrow = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(mq + 2 * (L + 1)) + 3) & ~(uintptr_t)3);
 
-    int total_sweeps = 0, maxsweep_hits = 0;
+    int total_sweeps = 0, maxsweep_hits = 0, redo_f64 = 0;
+    // the float32 Jacobi's sweep limit (one sweep when the float64 redo is
+    // forced, see TNMC_FORCE_F64_FALLBACK)
+    constexpr bool FLOAT_BUILD = std::is_same<T, float>::value;
+    const int jac_limit = (FLOAT_BUILD && (d.flags & 2)) ? 1 : MAX_SWEEPS;
     long long cyc_qr = 0, cyc_svd = 0, cyc_jac = 0, cyc_hh = 0;   // wall-clock ticks per phase
 
     // write one parity-basis site (from a generator) to the ping-pong buffer
@@ -1143,10 +1212,22 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
                 }
                 const int sw = jacobi_block<T, MAXB>(Tm + pb * bst, Wm + pb * bst, ldt, pb ? K1 : K0, n, chi,
                                                      tid & 63, wv >> 1, pb, jprm, jflag,
-                                                     nrm + pb * n, kr);
+                                                     nrm + pb * n, kr, jac_limit);
                 if ((tid & 63) == 0 && wv < 2) iflag[wv] = sw;
                 __syncthreads();
-                total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
+                const int swm = iflag[0] > iflag[1] ? iflag[0] : iflag[1];
+                total_sweeps += swm;
+                if constexpr (FLOAT_BUILD) {
+                    // orthogonality not reached in float32 (the last sweep
+                    // still rotated): redo the site's truncation in float64
+                    if (swm >= jac_limit) {
+                        double *fb = reinterpret_cast<double *>(qscr + (size_t)L * 4 * cc2);
+                        svd_redo_f64<MAXB>(fb, q, X, Tm, Wm, nrm, iflag, jflag, c, L, chi, K0, K1, r0, r1,
+                                           mq[2 * (c + 1)], mq[2 * (c + 1) + 1], n, kr, ldt, bst);
+                        total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
+                        ++redo_f64;
+                    }
+                }
                 maxsweep_hits += (iflag[0] >= MAX_SWEEPS) + (iflag[1] >= MAX_SWEEPS);
                 cyc_jac += wall_clock64() - t0;
             }
@@ -1268,6 +1349,7 @@ __device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsi
             so[STAT_MAXSWEEP] = maxsweep_hits;
             so[STAT_NONFINITE] = nonfinite;
             so[STAT_LOGZ_UNDEFINED] = nonfinite == 0 && !isfinite(lz);
+            so[STAT_FALLBACK] = redo_f64;
             so[0] = total_sweeps;
             so[1] = cyc_qr;
             so[2] = cyc_svd;

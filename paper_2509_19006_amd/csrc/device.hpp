@@ -30,9 +30,19 @@ static_assert(sizeof(InstDesc) == 96, "InstDesc layout");
 // truncations whose Jacobi stopped at the sweep limit without converging,
 // and rows whose log-scale is not finite; then 1 if the truncated network's
 // total (the contraction that gives ln Z) was not positive, so that ln Z is
-// not finite while the cache itself is sound.
+// not finite while the cache itself is sound; then (float builds) the
+// truncations whose float32 Jacobi did not converge and were redone in
+// float64.
 constexpr int STATS_PER_INST = 16;
-constexpr int STAT_MAXSWEEP = 8, STAT_NONFINITE = 9, STAT_LOGZ_UNDEFINED = 10;
+constexpr int STAT_MAXSWEEP = 8, STAT_NONFINITE = 9, STAT_LOGZ_UNDEFINED = 10, STAT_FALLBACK = 11;
+
+// Float64 redo of a float32 truncation (float builds only), per instance in
+// global memory after the build scratch: both blocks and their rotations
+// ([2][(chi+1)^2] doubles each), the split Jacobi's rotations in flight
+// ([2][2][32][2]) and the singular values ([2][chi+2]).
+__host__ __device__ constexpr size_t fallback_doubles(int chi) {
+    return (size_t)4 * (chi + 1) * (chi + 1) + 256 + 2 * (chi + 2);
+}
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) -----------------------------------
 struct U4 { uint32_t x, y, z, w; };

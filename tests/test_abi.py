@@ -116,6 +116,40 @@ def test_coupling_kind_is_validated(lib):
     assert e.value.code == T.TNMC_EINVAL
 
 
+def test_problem_flags_are_validated(lib):
+    for flags in (T.ALTERNATE_SWEEPS, T.FORCE_F64_FALLBACK, T.ALTERNATE_SWEEPS | T.FORCE_F64_FALLBACK):
+        p = T.Problem(None, None, [8], [8], [1.0], flags=flags)
+        assert T.tnmc_workspace_size(p, T.FP32, 8) > 0
+    p = T.Problem(None, None, [8], [8], [1.0], flags=4)
+    with pytest.raises(T.TnmcError) as e:
+        T.tnmc_workspace_size(p, T.FP32, 8)
+    assert e.value.code == T.TNMC_EINVAL
+
+
+def test_float_builds_reserve_the_float64_redo_area(lib):
+    """The workspace layout, written out for one instance: descriptor table,
+    launch order, build statistics, then log-scales, cache, build scratch
+    (Q slots and, in a float build, the float64 redo area: two blocks and
+    their rotations of (chi+1)^2 doubles each, 256 doubles of rotations in
+    flight, 2(chi+2) singular values), the parity-basis ping-pong, and one
+    sampler tile of right environments (256 samples); every part aligned to
+    256 bytes."""
+    up = lambda x: (x + 255) // 256 * 256
+    L, chi = 16, 8
+
+    def expect(ts, ss, redo):
+        fixed = up(96) + up(4) + up(8 * 16)
+        fixed += up(8 * L) + up(L * L * 2 * chi * chi * ss) + up(L * 4 * chi * chi * ts + redo)
+        fixed += up(2 * L * 2 * chi * chi * ts)
+        return fixed + up(256 * L * 16 * ts)
+
+    p = _problem((L,), (chi,), (1.0,))
+    redo = 8 * (4 * (chi + 1) ** 2 + 256 + 2 * (chi + 2))
+    assert T.tnmc_workspace_bytes(p, T.FP32, 8) == expect(4, 4, redo)
+    assert T.tnmc_workspace_bytes(p, T.MIXED_FP16, 8) == expect(4, 2, redo)
+    assert T.tnmc_workspace_bytes(p, T.FP64, 8) == expect(8, 8, 0)
+
+
 def _fake_problem(L, kind):
     """A problem whose device pointers are never dereferenced (the calls
     below fail validation before any device work)."""

@@ -335,3 +335,62 @@ def test_alternating_sweeps_match_the_oracle(G, tnmc, case):
     for i in range(len(Js)):
         print(f"  instance {i}: max relative log q error {np.max(rel_err(lq[i], want[i])):.2e}")
         assert np.max(rel_err(lq[i], want[i])) < tol
+
+
+REDO_CASES = [
+    # (name, L list, family, chi, beta, precision)
+    ("4x4 exact fp32", [4, 5], "gauss", 4, 1.5, 1),
+    ("16x16 chi32 fp32", [16, 16], "pmj", 32, 1.0, 1),
+    ("20x20 chi16 fp32", [20, 21], "gauss", 16, 1.0, 1),
+    ("20x20 chi40 fp32", [20, 20], "pmj", 40, 1.0, 1),
+    ("uneven L bf16x3", [2, 3, 9, 17], "pmj", 8, 0.7, 4),
+]
+
+
+@pytest.mark.parametrize("case", REDO_CASES, ids=[c[0] for c in REDO_CASES])
+def test_forced_float64_redo_matches_the_oracle(G, tnmc, case):
+    """The float64 redo of a float32 truncation whose Jacobi did not
+    converge: with TNMC_FORCE_F64_FALLBACK the float32 Jacobi stops after one
+    sweep, so every truncation that still rotates goes through the redo
+    (float64 centre from the float32 Q and carry, float64 Jacobi, results
+    back in float32).  ln Z and the teacher-forced log q of oracle draws stay
+    within the form's tolerance of the float64 oracle, the redo count is
+    recorded per instance and no float64 Jacobi reaches its limit."""
+    name, Ls, fam, chi, beta, prec = case
+    Js = [workloads.instance(L, fam, 47, i) for i, L in enumerate(Ls)]
+    G.say(f"forced float64 redo {name}: L={Ls} chi={chi} prec={prec}")
+    run = G.Run(Js, chi, beta, prec, max_samples=32, flags=tnmc.FORCE_F64_FALLBACK)
+    st = run.stats()
+    tnmc.tnmc_env_check(run.env)
+    tol = TOL[prec]
+    k = 12
+    forced, want = [], []
+    for i, (jh, jv) in enumerate(Js):
+        cache, _, lz = bmps.build_cache(beta, jh, jv, chi)
+        print(f"  instance {i}: ln Z {run.logz[i]:.12f} vs {lz:.12f}; {st[i, tnmc.STAT_FALLBACK]} redone "
+              f"truncations of {(Ls[i] - 1) * Ls[i]}")
+        assert rel_err(run.logz[i], lz) < tol
+        assert st[i, tnmc.STAT_MAXSWEEP] == 0
+        if Ls[i] >= 4:
+            assert st[i, tnmc.STAT_FALLBACK] > 0
+        bits, olq, _ = sampler.sample(cache, beta, jv, k, seed=47, instance=i)
+        forced.append(2 * bits - 1)
+        want.append(olq)
+    _, lq, _ = run.sample(k, forced=forced)
+    for i in range(len(Js)):
+        print(f"  instance {i}: max relative log q error {np.max(rel_err(lq[i], want[i])):.2e}")
+        assert np.max(rel_err(lq[i], want[i])) < tol
+    # without the flag the float32 Jacobi converges on these inputs: no redo
+    plain = G.Run(Js, chi, beta, prec, max_samples=4)
+    assert (plain.stats()[:, tnmc.STAT_FALLBACK] == 0).all()
+
+
+def test_float64_build_ignores_the_redo_flag(G, tnmc):
+    """TNMC_FORCE_F64_FALLBACK concerns the float builds only: a float64
+    build with it is bit-identical to one without."""
+    Js = [workloads.instance(10, "pmj", 48, i) for i in range(2)]
+    G.say("float64 build with the redo flag")
+    a = G.Run(Js, 8, 1.0, tnmc.FP64, max_samples=4, flags=tnmc.FORCE_F64_FALLBACK)
+    b = G.Run(Js, 8, 1.0, tnmc.FP64, max_samples=4)
+    assert np.array_equal(np.asarray(a.logz), np.asarray(b.logz))
+    assert (a.stats()[:, tnmc.STAT_FALLBACK] == 0).all()
