@@ -120,7 +120,11 @@ typedef struct tnmc_problem {
  * in the order the next row's QR sweep consumes them.  Another canonical
  * compression (section 2.2; the paper does not list its compress routine):
  * identical in the exact regime, different at the level of the truncation
- * error otherwise.  The cache is always stored in lattice order.           */
+ * error otherwise.  The cache is always stored in lattice order.  In the
+ * float builds with chi <= 32 (largest chi of the batch) this order also
+ * lets the build pipeline its rows: row r-1's QR sweep runs on two waves
+ * of the workgroup beside row r's SVD sweep on the other two, site by site
+ * (the workspace then holds two rows of QR scratch).                      */
 #define TNMC_ALTERNATE_SWEEPS 1
 
 /* Problem flag for the float builds: stop the float32 Jacobi after one
@@ -405,8 +409,10 @@ int tnmc_philox_uniform(uint64_t seed, const uint32_t *c0, uint32_t c1,
  * log-scales that are not finite; 1 if ln Z is undefined (the truncated
  * network's total was not positive); the number of truncations whose
  * float32 Jacobi did not converge and were redone in float64 (float builds;
- * slot 8 then counts the float64 Jacobi reaching its limit); slots 12-15
- * are zero.  The
+ * slot 8 then counts the float64 Jacobi reaching its limit); 1 if the
+ * row-pipelined build lost a hand-over between its waves (a bounded wait
+ * ran out; tnmc_env_check reports it as TNMC_ENUMERIC); slots 13-15 are
+ * zero.  The
  * build processes instances in decreasing order of estimated cost
  * (L-1) L chi^3.
  * NULL for a NULL env.                                                    */

@@ -296,7 +296,7 @@ def tnmc_philox_uniform(seed: int, c0, c1: int, c2: int, stream_id: int, out, st
 
 
 STATS_PER_INST = 16
-STAT_MAXSWEEP, STAT_NONFINITE, STAT_LOGZ_UNDEFINED, STAT_FALLBACK = 8, 9, 10, 11
+STAT_MAXSWEEP, STAT_NONFINITE, STAT_LOGZ_UNDEFINED, STAT_FALLBACK, STAT_PIPE_ERROR = 8, 9, 10, 11, 12
 
 
 def tnmc_env_stats(env: Env):

@@ -28,11 +28,12 @@ constexpr int kMlpRows = 64;
 constexpr int kMlpNParam = 8385;
 template <typename T, typename S>
 hipError_t launch_build(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
-                        double *, int64_t *, int, int, size_t, hipStream_t);
+                        double *, int64_t *, int, int, bool, size_t, hipStream_t);
 size_t build_lds_bytes(int chi, int L, size_t tsize);
+size_t build_pipe_lds_bytes(int chi, int L);
 template <typename T, typename S, bool SPLIT16>
 hipError_t launch_pipeline(const InstDesc *, const int32_t *, unsigned char *, const float *, const float *,
-                           double *, int64_t *, int, int, size_t, int, uint64_t, uint64_t, uint64_t *, double *,
+                           double *, int64_t *, int, int, bool, size_t, int, uint64_t, uint64_t, uint64_t *, double *,
                            double *, void *, uint64_t, uint64_t, uint8_t *, int64_t *, hipStream_t);
 template <typename T, typename S, bool SPLIT16>
 hipError_t launch_sample(int, int, const InstDesc *, unsigned char *, size_t, int, int, int, uint64_t,
@@ -110,7 +111,15 @@ struct Plan {
     size_t order_off = 0;
     size_t desc_off = 0, sweeps_off = 0, fixed = 0, tile_bytes = 0;
     int chi_bucket = 16, chi_max = 2, L_max = 2;
+    bool pipe = false;   // rows pipelined in the build (see build_pipe.hpp)
 };
+
+// Shared memory of the build kernels for a plan.
+size_t build_lds(const Plan &pl, int precision) {
+    size_t b = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
+    if (pl.pipe) b = std::max(b, tnmc::build_pipe_lds_bytes(pl.chi_max, pl.L_max));
+    return b;
+}
 
 int validate(const tnmc_problem *p, int precision, bool need_data) {
     if (!p) return fail(TNMC_EINVAL, "problem is NULL");
@@ -152,6 +161,10 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
         pl.L_max = std::max(pl.L_max, p->L[i]);
     }
     pl.chi_bucket = chi_bucket_of(pl.chi_max);
+    // the row-pipelined build: float arithmetic, chi <= 32 launches, and the
+    // alternating sweep order that lets row r-1's QR sweep follow row r's SVD
+    // sweep site by site
+    pl.pipe = (p->flags & TNMC_ALTERNATE_SWEEPS) && ts == sizeof(float) && pl.chi_max <= 32;
     size_t off = 0;
     pl.desc_off = off;
     off = align_up(off + sizeof(InstDesc) * B);
@@ -174,7 +187,7 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
     for (int i = 0; i < B; ++i) {
         InstDesc &d = pl.desc[i];
         const int L = p->L[i], chi = p->chi[i];
-        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = p->flags & (TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK);
+        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = (p->flags & (TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK)) | (pl.pipe ? tnmc::DESC_PIPE : 0);
         d.beta = p->beta[i];
         d.off_h = p->off_h ? p->off_h[i] : oh;
         d.off_v = p->off_v ? p->off_v[i] : ov;
@@ -188,8 +201,8 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
         off = align_up(off + sizeof(double) * L);
         d.cache_off = off;
         off = align_up(off + (size_t)L * L * 2 * chi * chi * ss);
-        d.qscr_off = off;      // Q slots, then (float builds) the float64 redo area
-        off = align_up(off + (size_t)L * 2 * 2 * chi * chi * ts +
+        d.qscr_off = off;      // Q slots (two rows when pipelined), then (float builds) the float64 redo area
+        off = align_up(off + (pl.pipe ? 2 : 1) * (size_t)L * 2 * 2 * chi * chi * ts +
                        (ts == sizeof(float) ? sizeof(double) * tnmc::fallback_doubles(chi) : 0));
         d.prev_off = off;      // previous row in the parity basis (build arithmetic type)
         off = align_up(off + (size_t)2 * L * 2 * chi * chi * ts);
@@ -204,8 +217,8 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
     return TNMC_OK;
 }
 
-int check_lds(int precision, int chi_max, int L_max) {
-    const size_t need = tnmc::build_lds_bytes(chi_max, L_max, tsize_of(precision));
+int check_lds(int precision, const Plan &pl) {
+    const size_t need = build_lds(pl, precision);
     int dev = 0, lim = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -256,7 +269,7 @@ int setup_env(const tnmc_problem *p, int32_t precision, void *workspace, size_t 
     plan(p, precision, pl, schedule);
     if (workspace_bytes < pl.fixed + pl.tile_bytes)
         return fail(TNMC_ENOSPACE, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs at least " + std::to_string(pl.fixed + pl.tile_bytes));
-    rc = check_lds(precision, pl.chi_max, pl.L_max);
+    rc = check_lds(precision, pl);
     if (rc) return rc;
     tnmc_env *env = new tnmc_env();
     env->batch = p->batch;
@@ -300,14 +313,14 @@ int tnmc_build_env(const tnmc_problem *p, int32_t precision, void *workspace, si
     const int32_t *ord = reinterpret_cast<const int32_t *>(env->ws + pl.order_off);
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
     int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
-    const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
+    const size_t lds = build_lds(pl, precision);
     hipError_t e;
     switch (precision) {
-    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
-    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
-    case TNMC_MIXED_BF16X3: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
-    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
-    default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, lds, st); break;
+    case TNMC_FP64: e = tnmc::launch_build<double, double>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, pl.pipe, lds, st); break;
+    case TNMC_FP32: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, pl.pipe, lds, st); break;
+    case TNMC_MIXED_BF16X3: e = tnmc::launch_build<float, float>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, pl.pipe, lds, st); break;
+    case TNMC_MIXED_BF16: e = tnmc::launch_build<float, __hip_bfloat16>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, pl.pipe, lds, st); break;
+    default: e = tnmc::launch_build<float, __half>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, pl.chi_max, pl.pipe, lds, st); break;
     }
     if (e != hipSuccess) { delete env; return hip_fail(e, "build launch"); }
     *env_out = env;
@@ -332,9 +345,9 @@ int tnmc_run(const tnmc_problem *p, int32_t precision, void *workspace, size_t w
     const int32_t *ord = reinterpret_cast<const int32_t *>(env->ws + pl.order_off);
     const InstDesc *dd = reinterpret_cast<const InstDesc *>(env->ws + pl.desc_off);
     int64_t *sw = reinterpret_cast<int64_t *>(env->ws + pl.sweeps_off);
-    const size_t lds = tnmc::build_lds_bytes(pl.chi_max, pl.L_max, tsize_of(precision));
+    const size_t lds = build_lds(pl, precision);
 #define TNMC_RUN(T, S, SP) tnmc::launch_pipeline<T, S, SP>(dd, ord, env->ws, p->J_h, p->J_v, logz_out, sw, p->batch, \
-        pl.chi_max, lds, n_samples, sample_seed, sample_offset, spins_out, logq_out, E_out, chain, accept_seed, \
+        pl.chi_max, pl.pipe, lds, n_samples, sample_seed, sample_offset, spins_out, logq_out, E_out, chain, accept_seed, \
         step_offset, accepted_out, state_out, st)
     hipError_t e;
     switch (precision) {
@@ -479,6 +492,8 @@ int tnmc_env_check(const tnmc_env *env, void *stream) {
         if (s[tnmc::STAT_NONFINITE])
             return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_NONFINITE]) +
                                            " row log-scale(s) not finite");
+        if (s[tnmc::STAT_PIPE_ERROR])
+            return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": the row-pipelined build lost a hand-over");
         if (s[tnmc::STAT_MAXSWEEP])
             return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_MAXSWEEP]) +
                                            " truncation(s) reached the Jacobi sweep limit");

@@ -874,7 +874,7 @@ __device__ void svd_redo_f64(double *fb, const float *q, const float *X, float *
 }
 
 template <typename T, typename S, int MAXB>
-__device__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
+__device__ __forceinline__ void build_instance(int inst, const InstDesc *__restrict__ desc, unsigned char *__restrict__ ws,
                                const float *__restrict__ Jh_all, const float *__restrict__ Jv_all,
                                double *__restrict__ logz_out, int64_t *__restrict__ stats_out,
                                unsigned char *smem) {

@@ -35,6 +35,15 @@ static_assert(sizeof(InstDesc) == 96, "InstDesc layout");
 // float64.
 constexpr int STATS_PER_INST = 16;
 constexpr int STAT_MAXSWEEP = 8, STAT_NONFINITE = 9, STAT_LOGZ_UNDEFINED = 10, STAT_FALLBACK = 11;
+// ... and 1 if the row-pipelined build lost a hand-over between its two roles
+// (a bounded wait ran out; the instance's cache is then not to be trusted).
+constexpr int STAT_PIPE_ERROR = 12;
+
+// Descriptor flag set by the host (beside the problem's TNMC_ALTERNATE_SWEEPS
+// and TNMC_FORCE_F64_FALLBACK): build the instance with rows pipelined (float
+// builds, chi <= 32, alternating sweeps); its build scratch then holds two
+// rows of Q slots.
+constexpr int DESC_PIPE = 4;
 
 // Float64 redo of a float32 truncation (float builds only), per instance in
 // global memory after the build scratch: both blocks and their rotations

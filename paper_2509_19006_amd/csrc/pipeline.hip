@@ -6,7 +6,7 @@
 // when its workgroup ends; nothing waits for the slowest instance of the
 // batch.  The arithmetic is the stand-alone kernels' (the same device
 // functions), so results equal the separate calls bit for bit.
-#include "build_device.hpp"
+#include "build_pipe.hpp"
 #include "energy_accept_device.hpp"
 #include "sample_device.hpp"
 #include "sample_mfma.hpp"
@@ -23,7 +23,7 @@ template <> struct PipeMode<__hip_bfloat16, false> { static constexpr int v = MF
 template <> struct PipeMode<__half, false> { static constexpr int v = MF_F16; };
 template <> struct PipeMode<double, false> { static constexpr int v = MF_F32; };
 
-template <typename T, typename S, int MAXB, bool SPLIT16>
+template <typename T, typename S, int MAXB, bool SPLIT16, bool PIPE>
 __global__ void __launch_bounds__(NT)
 k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order, unsigned char *__restrict__ ws,
            const float *__restrict__ Jh_all, const float *__restrict__ Jv_all, double *__restrict__ logz_out,
@@ -33,7 +33,7 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
            int64_t *__restrict__ state_out) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int inst = order[blockIdx.x];
-    build_instance<T, S, MAXB>(inst, desc, ws, Jh_all, Jv_all, logz_out, stats, smem);
+    build_instance_sel<T, S, MAXB, PIPE>(inst, desc, ws, Jh_all, Jv_all, logz_out, stats, smem);
     __threadfence();
     __syncthreads();
 
@@ -90,13 +90,13 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
     }
 }
 
-template <typename T, typename S, int MAXB, bool SPLIT16>
+template <typename T, typename S, int MAXB, bool SPLIT16, bool PIPE>
 hipError_t launch_pipeline_w(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
                              const float *Jv, double *logz, int64_t *stats, int B, size_t lds_bytes,
                              int n_samples, uint64_t sseed, uint64_t soff, uint64_t *spins, double *logq, double *E,
                              void *chain, uint64_t aseed, uint64_t aoff, uint8_t *acc, int64_t *state,
                              hipStream_t st) {
-    auto kern = k_pipeline<T, S, MAXB, SPLIT16>;
+    auto kern = k_pipeline<T, S, MAXB, SPLIT16, PIPE>;
     // room for the matrix-core sampler's staging as well
     constexpr size_t stage = mf_lds_bytes<32, S, PipeMode<S, SPLIT16>::v>();
     if (lds_bytes < stage) lds_bytes = stage;
@@ -109,27 +109,36 @@ hipError_t launch_pipeline_w(const InstDesc *desc, const int32_t *order, unsigne
 
 template <typename T, typename S, bool SPLIT16>
 hipError_t launch_pipeline(const InstDesc *desc, const int32_t *order, unsigned char *ws, const float *Jh,
-                           const float *Jv, double *logz, int64_t *stats, int B, int chi_max, size_t lds_bytes,
-                           int n_samples, uint64_t sseed, uint64_t soff, uint64_t *spins, double *logq, double *E,
-                           void *chain, uint64_t aseed, uint64_t aoff, uint8_t *acc, int64_t *state,
-                           hipStream_t st) {
+                           const float *Jv, double *logz, int64_t *stats, int B, int chi_max, bool pipe,
+                           size_t lds_bytes, int n_samples, uint64_t sseed, uint64_t soff, uint64_t *spins,
+                           double *logq, double *E, void *chain, uint64_t aseed, uint64_t aoff, uint8_t *acc,
+                           int64_t *state, hipStream_t st) {
     if constexpr (sizeof(T) == 8) {
-        if (chi_max > 32) return hipErrorInvalidValue;
-        return launch_pipeline_w<T, S, 32, SPLIT16>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples, sseed,
-                                           soff, spins, logq, E, chain, aseed, aoff, acc, state, st);
+        if (chi_max > 32 || pipe) return hipErrorInvalidValue;
+        return launch_pipeline_w<T, S, 32, SPLIT16, false>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes,
+                                                           n_samples, sseed, soff, spins, logq, E, chain, aseed,
+                                                           aoff, acc, state, st);
     } else {
+        if (pipe) {
+            if (chi_max > 32) return hipErrorInvalidValue;
+            return launch_pipeline_w<T, S, 32, SPLIT16, true>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes,
+                                                              n_samples, sseed, soff, spins, logq, E, chain, aseed,
+                                                              aoff, acc, state, st);
+        }
         if (chi_max <= 32)
-            return launch_pipeline_w<T, S, 32, SPLIT16>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples,
-                                               sseed, soff, spins, logq, E, chain, aseed, aoff, acc, state, st);
-        return launch_pipeline_w<T, S, 64, SPLIT16>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes, n_samples, sseed,
-                                           soff, spins, logq, E, chain, aseed, aoff, acc, state, st);
+            return launch_pipeline_w<T, S, 32, SPLIT16, false>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes,
+                                                               n_samples, sseed, soff, spins, logq, E, chain, aseed,
+                                                               aoff, acc, state, st);
+        return launch_pipeline_w<T, S, 64, SPLIT16, false>(desc, order, ws, Jh, Jv, logz, stats, B, lds_bytes,
+                                                           n_samples, sseed, soff, spins, logq, E, chain, aseed, aoff,
+                                                           acc, state, st);
     }
 }
 
 #define TNMC_LP(T, S, SP)                                                                                     \
     template hipError_t launch_pipeline<T, S, SP>(const InstDesc *, const int32_t *, unsigned char *,            \
                                                   const float *, const float *, double *, int64_t *, int, int,   \
-                                                  size_t, int, uint64_t, uint64_t, uint64_t *, double *, double *, \
+                                                  bool, size_t, int, uint64_t, uint64_t, uint64_t *, double *, double *, \
                                                   void *, uint64_t, uint64_t, uint8_t *, int64_t *, hipStream_t);
 TNMC_LP(double, double, false)
 TNMC_LP(float, float, false)

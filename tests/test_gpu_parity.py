@@ -307,6 +307,11 @@ ALT_CASES = [
     ("uneven L", [2, 3, 9, 17], "pmj", 8, 0.7, 0),
     ("20x20 chi16 fp32", [20, 21], "gauss", 16, 1.0, 1),
     ("20x20 chi40 fp32", [20, 20], "pmj", 40, 1.0, 1),
+    # float, chi <= 32: the row-pipelined build
+    ("16x16 chi32 fp32", [16, 16], "pmj", 32, 1.0, 1),
+    ("uneven L fp32", [2, 3, 9, 17], "pmj", 8, 0.7, 1),
+    ("24x24 chi32 bf16x3", [24, 23], "gauss", 32, 1.0, 4),
+    ("16x16 chi32 fp16", [16, 16], "pmj", 32, 1.0, 3),
 ]
 
 
@@ -394,3 +399,26 @@ def test_float64_build_ignores_the_redo_flag(G, tnmc):
     b = G.Run(Js, 8, 1.0, tnmc.FP64, max_samples=4)
     assert np.array_equal(np.asarray(a.logz), np.asarray(b.logz))
     assert (a.stats()[:, tnmc.STAT_FALLBACK] == 0).all()
+
+
+def test_pipelined_build_redo_and_reproducibility(G, tnmc):
+    """The row-pipelined build (float, chi <= 32, alternating sweeps) with
+    every truncation sent through the float64 redo matches the oracle's
+    alternating compression, and is bit-reproducible run to run; no
+    hand-over between its two roles is lost."""
+    Js = [workloads.instance(L, "pmj", 49, i) for i, L in enumerate([12, 17])]
+    chi, beta = 16, 1.0
+    G.say("pipelined build with the float64 redo forced")
+    flags = tnmc.ALTERNATE_SWEEPS | tnmc.FORCE_F64_FALLBACK
+    a = G.Run(Js, chi, beta, tnmc.FP32, max_samples=16, flags=flags)
+    b = G.Run(Js, chi, beta, tnmc.FP32, max_samples=16, flags=flags)
+    st = a.stats()
+    tnmc.tnmc_env_check(a.env)
+    assert np.array_equal(np.asarray(a.logz), np.asarray(b.logz))
+    for i, (jh, jv) in enumerate(Js):
+        _, _, lz = bmps.build_cache(beta, jh, jv, chi, alternate=True)
+        assert rel_err(a.logz[i], lz) < TOL[1]
+        assert st[i, tnmc.STAT_FALLBACK] > 0 and st[i, tnmc.STAT_PIPE_ERROR] == 0
+    _, lq_a, _ = a.sample(16, seed=3)
+    _, lq_b, _ = b.sample(16, seed=3)
+    assert np.array_equal(np.asarray(lq_a), np.asarray(lq_b))
