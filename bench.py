@@ -43,7 +43,7 @@ PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "mfma16": 2.5e15, "hbm": 8.0e12}
 TRAFFIC_PROFILE = "profiles/k_build_k_sample_mfma_256x256_chi32_hbm_traffic.txt"
 TRAFFIC = {
     "k_build": {"sources": ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
-                            "paper_2509_19006_amd/csrc/device.hpp"],
+                            "paper_2509_19006_amd/csrc/build_pipe.hpp", "paper_2509_19006_amd/csrc/device.hpp"],
                 "sha256": "ba5579ad6342450d02df08bf1f304af31e9372ca79ed375139f599c0af2d53e0",
                 "bytes": {"fp32": 939003884802, "bf16x3": 939003884802,
                           "fp16": 870267542202}},
@@ -111,8 +111,8 @@ def sample_bytes(L, chi, B, N, cache_elem_bytes):
     return B * L * L * 2 * chi ** 2 * cache_elem_bytes + B * N * L * ((L + 63) // 64) * 8
 
 
-def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed):
-    problem = T.Problem(jh, jv, [L] * B, chi, beta, coupling_kind=T.COUPLING_PMJ)
+def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed, flags=0):
+    problem = T.Problem(jh, jv, [L] * B, chi, beta, coupling_kind=T.COUPLING_PMJ, flags=flags)
     nbytes = T.tnmc_workspace_size(problem, prec, N)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     words = N * problem.spin_words_per_sample()
@@ -201,7 +201,7 @@ def cpu_model():
 CPU_SAMPLE_L = 96
 
 
-def cpu_baseline_child(L, chi, beta, n_sample, L_full):
+def cpu_baseline_child(L, chi, beta, n_sample, L_full, alternate=False):
     """The oracle end to end on one instance (the first disorder of a batch
     of side L): the float64 cache build of all L - 1 rows, n_sample draws,
     their energies and the Metropolis chain over them.  Prints progress to
@@ -218,7 +218,7 @@ def cpu_baseline_child(L, chi, beta, n_sample, L_full):
     jh, jv = workloads.batch(L, 1, "pmj", 3)
     jh, jv = jh[0].astype(np.float64), jv[0].astype(np.float64)
     t0 = time.perf_counter()
-    cache, _, _ = bmps.build_cache(beta, jh, jv, chi)
+    cache, _, _ = bmps.build_cache(beta, jh, jv, chi, alternate=alternate)
     t_build = time.perf_counter() - t0
     log(f"  oracle leg: cache build of {L - 1} rows done ({t_build:.1f} s)")
     bits, logq, _ = sampler.sample(cache, beta, jv, n_sample, seed=0x5A5A0003)
@@ -235,7 +235,8 @@ def cpu_baseline_child(L, chi, beta, n_sample, L_full):
                       "acceptance": chain.n_acc / max(1, chain.n_trials), "trials": chain.n_trials,
                       "wall_s": wall, "build_s": t_build,
                       "sample": (f"one {L}x{L} +-J instance of the workload's family (chi={chi}, beta={beta}): "
-                                 f"the float64 cache build of all {L - 1} rows ({t_build:.1f} s), {n_sample} "
+                                 f"the float64 cache build of all {L - 1} rows ({'alternating' if alternate else 'plain'} "
+                                 f"sweep order) ({t_build:.1f} s), {n_sample} "
                                  f"draws, their energies and the oracle's own Metropolis chain "
                                  f"({chain.n_acc} of {chain.n_trials} trials accepted), timed end to end; "
                                  f"the rate scaled to {L_full}x{L_full} by the site-row ratio "
@@ -243,13 +244,14 @@ def cpu_baseline_child(L, chi, beta, n_sample, L_full):
           flush=True)
 
 
-def start_cpu_baseline(L, chi, beta, n_sample=8):
+def start_cpu_baseline(L, chi, beta, n_sample=8, alternate=False):
     """Starts the oracle leg as a child process before this process touches
     the GPU; collect it with finish_cpu_baseline."""
     import subprocess
     Ls = min(L, CPU_SAMPLE_L)
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--L", str(Ls), "--chi", str(chi),
-           "--beta", str(beta), "--samples", str(n_sample), "--full-L", str(L)]
+           "--beta", str(beta), "--samples", str(n_sample), "--full-L", str(L),
+           "--sweeps", "alternating" if alternate else "plain"]
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)
 
 
@@ -614,6 +616,9 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3,fp16",
                     help="precision forms of the headline workload, comma separated (the first is fp32): "
                          "fp32, bf16x3, fp16, bf16")
+    ap.add_argument("--sweeps", choices=["alternating", "plain"], default="alternating",
+                    help="compression sweep order of the cache build: alternating (every second row "
+                         "mirrored; float builds with chi <= 32 then pipeline their rows) or plain")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--full-L", type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -636,7 +641,8 @@ def main():
         if getattr(args, k) is None:
             setattr(args, k, v)
     if args.cpu_baseline_child:
-        cpu_baseline_child(args.L, args.chi, args.beta, args.samples, args.full_L or args.L)
+        cpu_baseline_child(args.L, args.chi, args.beta, args.samples, args.full_L or args.L,
+                           alternate=args.sweeps == "alternating")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the instances are independent and this build runs "
@@ -646,7 +652,7 @@ def main():
     cpu_proc = None
     if args.workload == "headline" and not args.no_cpu_baseline:
         # the oracle leg runs on the host cores while the GPU forms run
-        cpu_proc = start_cpu_baseline(args.L, args.chi, args.beta)
+        cpu_proc = start_cpu_baseline(args.L, args.chi, args.beta, alternate=args.sweeps == "alternating")
     import numpy as np
     import torch
     if args.copy_probe > 0:
@@ -689,7 +695,8 @@ def main():
              "fp16": "float16-stored cache", "bf16": "bfloat16-stored cache"}
     for f in args.forms.split(","):
         log(f"{names[f]} form:")
-        forms[f] = run_form(T, torch, T.PRECISIONS[f], jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed)
+        forms[f] = run_form(T, torch, T.PRECISIONS[f], jh, jv, L, chi, beta, B, N, args.steps, args.warmup, seed,
+                            flags=T.ALTERNATE_SWEEPS if args.sweeps == "alternating" else 0)
     plain = forms["fp32"]
 
     # the dominant kernel: the cache build (float32 vector ALU, latency bound)
@@ -740,9 +747,12 @@ def main():
         "ms_per_step": plain["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"TNMC on {L}x{L} open +-J EA lattices, beta={beta}, chi={chi}, {B} disorders x "
-                                f"{N} samples: float32 build and sampler, float64 log-weights and accept, int32 "
-                                f"energies; beside it the other precision forms on the same inputs"),
-                   "L": L, "chi": chi, "disorders": B, "samples": N, "beta": beta, "form": "plain-fp32"},
+                                f"{N} samples: float32 build ({args.sweeps} sweep order"
+                                f"{', rows pipelined' if args.sweeps == 'alternating' and chi <= 32 else ''}) and "
+                                f"sampler, float64 log-weights and accept, int32 energies; beside it the other "
+                                f"precision forms on the same inputs"),
+                   "L": L, "chi": chi, "disorders": B, "samples": N, "beta": beta, "form": "plain-fp32",
+                   "sweeps": args.sweeps},
         "acceptance": plain["acceptance"],
         "forms": forms,
         "roofline": roof, "roofline_sample": roof_sample, "cpu_baseline": cpu,

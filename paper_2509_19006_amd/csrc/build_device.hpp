@@ -1350,6 +1350,9 @@ __device__ __forceinline__ void build_instance(int inst, const InstDesc *__restr
             so[STAT_NONFINITE] = nonfinite;
             so[STAT_LOGZ_UNDEFINED] = nonfinite == 0 && !isfinite(lz);
             so[STAT_FALLBACK] = redo_f64;
+            // the rest of the record (the row-pipelined build's hand-over
+            // flag, spare slots) is defined as zero here
+            for (int k = STAT_FALLBACK + 1; k < STATS_PER_INST; ++k) so[k] = 0;
             so[0] = total_sweeps;
             so[1] = cyc_qr;
             so[2] = cyc_svd;

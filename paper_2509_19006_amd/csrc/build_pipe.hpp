@@ -755,6 +755,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
             so[STAT_LOGZ_UNDEFINED] = nonfinite == 0 && !isfinite(lz);
             so[STAT_FALLBACK] = iflag[2];
             so[STAT_PIPE_ERROR] = pipe_ld(perr);
+            for (int k = STAT_PIPE_ERROR + 1; k < STATS_PER_INST; ++k) so[k] = 0;
             so[0] = iflag[0];
             so[1] = cycq[0];
             so[2] = reinterpret_cast<long long *>(scal)[5];

@@ -28,12 +28,15 @@ sys.path.insert(0, ROOT)
 import workloads                                   # noqa: E402
 from oracle import bmps, sampler                   # noqa: E402
 
-# (file, family, L, config id, instance indices, chi, beta, draws, seed)
+# (file, family, L, config id, instance indices, chi, beta, draws, seed,
+#  alternating sweep order)
 RECORDS = [
     # the headline batch: instances 0 and 1 of the 256 +-J disorders of 256x256
-    ("fullsize_256_chi32.json", "pmj", 256, 3, (0, 1), 32, 1.0, 3, 0x0C3),
+    ("fullsize_256_chi32.json", "pmj", 256, 3, (0, 1), 32, 1.0, 3, 0x0C3, False),
+    # the same instances compressed in the alternating sweep order
+    ("fullsize_256_chi32_alt.json", "pmj", 256, 3, (0, 1), 32, 1.0, 3, 0x0C3, True),
     # the paper's run: +-J EA, 1024x1024, beta = 1, chi = 8
-    ("paper_1024_chi8.json", "pmj", 1024, 7, (0,), 8, 1.0, 1, 0x1024),
+    ("paper_1024_chi8.json", "pmj", 1024, 7, (0,), 8, 1.0, 1, 0x1024, False),
 ]
 
 
@@ -48,14 +51,14 @@ def unpack_bits(text: str, n: int, L: int) -> np.ndarray:
     return np.unpackbits(raw.reshape(n, L, -1), axis=-1, count=L, bitorder="little").astype(np.int64)
 
 
-def make(name, family, L, cfg, idx, chi, beta, draws, seed):
+def make(name, family, L, cfg, idx, chi, beta, draws, seed, alternate):
     out = {"family": family, "L": L, "config_id": cfg, "chi": chi, "beta": beta, "draws": draws,
-           "seed": seed, "instances": []}
+           "seed": seed, "alternate": alternate, "instances": []}
     for i in idx:
         jh, jv = workloads.instance(L, family, cfg, i)
         t0 = time.time()
         dg = {}
-        cache, _, logz = bmps.build_cache(beta, jh, jv, chi, dg)
+        cache, _, logz = bmps.build_cache(beta, jh, jv, chi, dg, alternate=alternate)
         t1 = time.time()
         bits, logq, _ = sampler.sample(cache, beta, jv, draws, seed=seed, instance=i)
         print(f"{name}: instance {i} build {t1 - t1 + (t1 - t0):.0f} s, sampling {time.time() - t1:.0f} s",

@@ -150,6 +150,24 @@ def test_float_builds_reserve_the_float64_redo_area(lib):
     assert T.tnmc_workspace_bytes(p, T.FP64, 8) == expect(8, 8, 0)
 
 
+def test_pipelined_build_doubles_the_q_slots(lib):
+    """With alternating sweeps a float build of chi <= 32 pipelines its rows
+    and keeps two rows of Q slots; float64 builds, and batches with chi > 32,
+    keep one."""
+    up = lambda x: (x + 255) // 256 * 256
+    L, chi = 16, 8
+    qrow = L * 4 * chi * chi * 4
+    redo = 8 * (4 * (chi + 1) ** 2 + 256 + 2 * (chi + 2))
+    plain = T.Problem(None, None, [L], [chi], [1.0])
+    alt = T.Problem(None, None, [L], [chi], [1.0], flags=T.ALTERNATE_SWEEPS)
+    d32 = T.tnmc_workspace_bytes(alt, T.FP32, 8) - T.tnmc_workspace_bytes(plain, T.FP32, 8)
+    assert d32 == up(2 * qrow + redo) - up(qrow + redo)
+    assert T.tnmc_workspace_bytes(alt, T.FP64, 8) == T.tnmc_workspace_bytes(plain, T.FP64, 8)
+    wide = T.Problem(None, None, [L, L], [chi, 40], [1.0, 1.0], flags=T.ALTERNATE_SWEEPS)
+    wide0 = T.Problem(None, None, [L, L], [chi, 40], [1.0, 1.0])
+    assert T.tnmc_workspace_bytes(wide, T.FP32, 8) == T.tnmc_workspace_bytes(wide0, T.FP32, 8)
+
+
 def _fake_problem(L, kind):
     """A problem whose device pointers are never dereferenced (the calls
     below fail validation before any device work)."""

@@ -143,3 +143,38 @@ def test_full_size_batch_forms_against_stored_oracle(tnmc):
             assert eq < TOL[prec]
         del run
         torch.cuda.empty_cache()
+
+
+def test_full_size_pipelined_build_against_stored_oracle(tnmc):
+    """The benchmark's launch configuration with the alternating sweep order
+    (256 +-J disorders of 256 x 256, chi 32, 256 samples; the float builds
+    then pipeline their rows) in float32, the mixed form and the float16
+    cache: the two stored instances' ln Z and teacher-forced log q against
+    the oracle's alternating compression; no hand-over lost."""
+    import torch
+    import tnmc_gpu as G
+    g = golden("fullsize_256_chi32_alt.json")
+    assert g["alternate"]
+    L, chi, beta, k = g["L"], g["chi"], g["beta"], g["draws"]
+    B, N = 256, 256
+    jh, jv = workloads.batch(L, B, g["family"], g["config_id"])
+    Js = [(jh[i], jv[i]) for i in range(B)]
+    for prec in (tnmc.FP32, tnmc.MIXED_BF16X3, tnmc.MIXED_FP16):
+        G.say(f"full size, alternating sweeps: {B} x {L}x{L}, chi {chi}, prec {prec}")
+        run = G.Run(Js, chi, beta, prec, max_samples=N, flags=tnmc.ALTERNATE_SWEEPS)
+        tnmc.tnmc_env_check(run.env)
+        assert (run.stats()[:, tnmc.STAT_PIPE_ERROR] == 0).all()
+        forced = [np.zeros((k, L, L), np.int8) + 1 for _ in range(B)]
+        for inst in g["instances"]:
+            forced[inst["index"]] = inst["spins"]
+        _, lq_o, _ = run.sample(k, forced=forced)
+        for inst in g["instances"]:
+            i = inst["index"]
+            ez = rel_err(run.logz[i], inst["logz"])
+            eq = rel_err(lq_o[i], inst["logq"]).max()
+            print(f"  instance {i}: ln Z relative error {ez:.2e}, log q relative error {eq:.2e} "
+                  f"(cut conditioning {inst['cond']:.1e})")
+            assert ez < TOL[1]
+            assert eq < TOL[prec]
+        del run
+        torch.cuda.empty_cache()

@@ -96,12 +96,14 @@ def test_decode_steps_replay_from_a_graph(tnmc):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 3, 4])
-def test_fused_pipeline_equals_separate_calls(tnmc, prec):
+@pytest.mark.parametrize("prec,alt", [(0, False), (1, False), (3, False), (4, False), (1, True), (3, True), (4, True)])
+def test_fused_pipeline_equals_separate_calls(tnmc, prec, alt):
     """tnmc_run (build, sampling tiles, energies and the chain in one
     persistent launch) gives bit-identical results to tnmc_build_env +
     tnmc_sample + tnmc_energy + tnmc_accept on an uneven batch; 300 samples
-    span two sample tiles, run one after the other in the fused launch."""
+    span two sample tiles, run one after the other in the fused launch.
+    With alternating sweeps the float forms build with rows pipelined in
+    both."""
     import torch
     import tnmc_gpu as G
     Ls = [6, 12, 20, 9, 16, 24]
@@ -109,10 +111,10 @@ def test_fused_pipeline_equals_separate_calls(tnmc, prec):
     fams = ["pmj", "gauss", "pmj", "gauss", "gauss", "pmj"]
     betas = workloads.betas_uniform(len(Ls), 0.5, 2.0, 92)
     Js = [workloads.instance(L, f, 92, i) for i, (L, f) in enumerate(zip(Ls, fams))]
-    G.say(f"fused pipeline vs separate calls, prec {prec}")
+    G.say(f"fused pipeline vs separate calls, prec {prec}, alternating {alt}")
     jh = torch.as_tensor(np.concatenate([a.ravel() for a, _ in Js])).cuda()
     jv = torch.as_tensor(np.concatenate([b.ravel() for _, b in Js])).cuda()
-    p = tnmc.Problem(jh, jv, Ls, chis, betas)
+    p = tnmc.Problem(jh, jv, Ls, chis, betas, flags=tnmc.ALTERNATE_SWEEPS if alt else 0)
     B, n = len(Ls), 300
     out = []
     for fused in (False, True):
