@@ -44,23 +44,27 @@ TRAFFIC_PROFILE = "profiles/k_build_k_sample_mfma_256x256_chi32_hbm_traffic.txt"
 TRAFFIC = {
     "k_build": {"sources": ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
                             "paper_2509_19006_amd/csrc/build_pipe.hpp", "paper_2509_19006_amd/csrc/device.hpp"],
-                "sha256": "ba5579ad6342450d02df08bf1f304af31e9372ca79ed375139f599c0af2d53e0",
-                "bytes": {"fp32": 939003884802, "bf16x3": 939003884802,
-                          "fp16": 870267542202}},
+                "sha256": "4b7d2fb3ccdeee00aa82f45e885118f55e033c461d51b9c2032fa93a1adae27d",
+                "sweeps": "alternating",
+                "bytes": {"fp32": 881139156536, "bf16x3": 881139156536,
+                          "fp16": 795181737288}},
     "k_sample_mfma": {"sources": ["paper_2509_19006_amd/csrc/sample.hip", "paper_2509_19006_amd/csrc/sample_mfma.hpp",
                                   "paper_2509_19006_amd/csrc/device.hpp"],
-                      "sha256": "06f9a640028de95975a2c771abf3075942ce2921f4bb7bc87d8754a321b87571",
-                      "bytes": {"fp32": 1388337726130, "bf16x3": 1388221583791,
-                                "fp16": 1250828227911}},
+                      "sha256": "1602b9d23a3f37cc222099c214d18bb5635cce011dfcf49f1240a5c754ac5939",
+                      "bytes": {"fp32": 1388361258775, "bf16x3": 1388207636577,
+                                "fp16": 1250852210769}},
 }
 
 
-def traffic_for(kernel, form):
-    """Counter-measured HBM bytes of one launch of kernel in the given form,
-    or None when the kernel's source has changed since the measurement."""
+def traffic_for(kernel, form, sweeps=None):
+    """Counter-measured HBM bytes of one launch of kernel in the given form
+    (and, for the build, sweep order), or None when the kernel's source has
+    changed since the measurement."""
     import hashlib
     ent = TRAFFIC.get(kernel)
     if ent is None or form not in ent["bytes"]:
+        return None
+    if "sweeps" in ent and sweeps != ent["sweeps"]:
         return None
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
@@ -708,7 +712,7 @@ def main():
     roof = {"bound": "alu", "kernel": "k_build (cache build, float32 arithmetic)",
             "achieved": ex / t_build / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
             "frac": ex / t_build / PEAK["fp32"],
-            "traffic": traffic_for("k_build", "fp32") if default_size else None,
+            "traffic": traffic_for("k_build", "fp32", args.sweeps) if default_size else None,
             "traffic_profile": TRAFFIC_PROFILE,
             "flops_per_launch": ex,
             "per_unit": (f"(2 chi^2 +) (25.3 + 14 S) chi^3 flop per site-row executed by the parity-block "
