@@ -111,7 +111,8 @@ typedef struct tnmc_problem {
     const int64_t *off_h;   /* host [B] or NULL: element offset of instance i */
     const int64_t *off_v;   /*   in J_h / J_v; NULL = packed in batch order   */
     int32_t coupling_kind;  /* TNMC_COUPLING_*, declares the exact-energy mode */
-    int32_t flags;          /* 0 or TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK */
+    int32_t flags;          /* TNMC_ALTERNATE_SWEEPS, TNMC_FORCE_F64_FALLBACK,  */
+                            /* TNMC_SHORT_WAITS, or 0                         */
 } tnmc_problem;
 
 /* Problem flag: the compression of every second row (the rows L-3, L-5, ...
@@ -132,6 +133,13 @@ typedef struct tnmc_problem {
  * float64 redo (an exercise of that path: the build slows down, results
  * stay within the float forms' tolerance).  No effect on TNMC_FP64.       */
 #define TNMC_FORCE_F64_FALLBACK 2
+
+/* Problem flag, a test of the row-pipelined build's failure path: every
+ * hand-over wait between its two pairs of waves gives up after one poll,
+ * so the build soon records a lost hand-over, finishes without waiting
+ * (its cache is then not to be used) and tnmc_env_check reports
+ * TNMC_ENUMERIC.  No effect on the other builds.                           */
+#define TNMC_SHORT_WAITS 8
 
 /* Per-instance Metropolis chain state (device memory, caller owned).
  * Zero-fill before the first tnmc_accept call of a chain.                */

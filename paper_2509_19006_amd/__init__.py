@@ -18,6 +18,7 @@ TNMC_OK, TNMC_EINVAL, TNMC_ENOSPACE, TNMC_EHIP, TNMC_ENOTSUP, TNMC_ENUMERIC = 0,
 COUPLING_GENERAL, COUPLING_PMJ, COUPLING_GRID20 = 0, 1, 2
 ALTERNATE_SWEEPS = 1
 FORCE_F64_FALLBACK = 2
+SHORT_WAITS = 8
 FP64, FP32, MIXED_BF16, MIXED_FP16, MIXED_BF16X3 = 0, 1, 2, 3, 4
 SCHED_LONGEST_FIRST, SCHED_SHORTEST_FIRST, SCHED_AS_GIVEN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16, "bf16x3": MIXED_BF16X3}

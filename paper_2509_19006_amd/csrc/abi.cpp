@@ -143,7 +143,8 @@ int validate(const tnmc_problem *p, int precision, bool need_data) {
     }
     if (p->coupling_kind < TNMC_COUPLING_GENERAL || p->coupling_kind > TNMC_COUPLING_GRID20)
         return fail(TNMC_EINVAL, "unknown coupling_kind");
-    if (p->flags & ~(TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK)) return fail(TNMC_EINVAL, "unknown problem flags");
+    if (p->flags & ~(TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK | TNMC_SHORT_WAITS))
+        return fail(TNMC_EINVAL, "unknown problem flags");
     return TNMC_OK;
 }
 
@@ -187,7 +188,8 @@ int plan(const tnmc_problem *p, int precision, Plan &pl, int schedule = TNMC_SCH
     for (int i = 0; i < B; ++i) {
         InstDesc &d = pl.desc[i];
         const int L = p->L[i], chi = p->chi[i];
-        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = (p->flags & (TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK)) | (pl.pipe ? tnmc::DESC_PIPE : 0);
+        d.L = L; d.chi = chi; d.W = (L + 63) / 64; d.flags = (p->flags & (TNMC_ALTERNATE_SWEEPS | TNMC_FORCE_F64_FALLBACK | TNMC_SHORT_WAITS)) |
+                  (pl.pipe ? tnmc::DESC_PIPE : 0);
         d.beta = p->beta[i];
         d.off_h = p->off_h ? p->off_h[i] : oh;
         d.off_v = p->off_v ? p->off_v[i] : ov;
@@ -489,11 +491,13 @@ int tnmc_env_check(const tnmc_env *env, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "statistics read");
     for (int i = 0; i < env->batch; ++i) {
         const int64_t *s = st.data() + (size_t)tnmc::STATS_PER_INST * i;
+        // a lost hand-over first: the other counts of that build are its
+        // consequences
+        if (s[tnmc::STAT_PIPE_ERROR])
+            return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": the row-pipelined build lost a hand-over");
         if (s[tnmc::STAT_NONFINITE])
             return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_NONFINITE]) +
                                            " row log-scale(s) not finite");
-        if (s[tnmc::STAT_PIPE_ERROR])
-            return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": the row-pipelined build lost a hand-over");
         if (s[tnmc::STAT_MAXSWEEP])
             return fail(TNMC_ENUMERIC, "instance " + std::to_string(i) + ": " + std::to_string(s[tnmc::STAT_MAXSWEEP]) +
                                            " truncation(s) reached the Jacobi sweep limit");

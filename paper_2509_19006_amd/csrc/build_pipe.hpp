@@ -29,6 +29,10 @@
 // instance's statistics record the failure (slot 12, reported by
 // tnmc_env_check), so a broken hand-over never hangs the workgroup.
 //
+// Sector sizes read from shared memory are clamped to their bounds (no-ops
+// for a sound hand-over): after a lost hand-over the roles run on without
+// each other's data, and the clamps keep every access inside its buffer.
+//
 // Used for float builds with chi <= 32 when the problem asks for
 // alternating sweeps (the host sets the descriptor flag DESC_PIPE and
 // sizes the workspace and shared memory for it).
@@ -49,12 +53,13 @@ __device__ __forceinline__ void pipe_st(int *p, int v) {
     __hip_atomic_store((lds_int *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Waits until *word >= target, then orders every later access after it.
-__device__ __forceinline__ void pipe_wait(int *word, int target, int *err) {
+// Waits until *word >= target (at most limit polls), then orders every
+// later access after it.
+__device__ __forceinline__ void pipe_wait(int *word, int target, int *err, int limit) {
     int polls = 0;
     while (pipe_ld(word) < target) {
         if (pipe_ld(err)) break;
-        if (++polls > PIPE_WAIT_LIMIT) { pipe_st(err, 1); break; }
+        if (++polls > limit) { pipe_st(err, 1); break; }
         __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -72,13 +77,14 @@ struct RoleSync {
     int *err;      // sticky error word
     double *red;   // [2]
     int phase;     // arrivals this role has waited for so far
+    int limit;     // polls before a wait gives up
 };
 __device__ __forceinline__ void role_sync(RoleSync &rs) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if ((threadIdx.x & 63) == 0)
         __hip_atomic_fetch_add((lds_int *)rs.bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     rs.phase += 2;
-    pipe_wait(rs.bar, rs.phase, rs.err);
+    pipe_wait(rs.bar, rs.phase, rs.err, rs.limit);
 }
 __device__ __forceinline__ double role_sum(double v, RoleSync &rs) {
     v = group_sum(v, 64);
@@ -403,6 +409,9 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
     float *jrow = reinterpret_cast<float *>((reinterpret_cast<uintptr_t>(mqb + 4 * (L + 1)) + 3) & ~(uintptr_t)3);
 
     const bool alternate = (d.flags & 1) != 0;
+    // polls before a hand-over wait gives up (one with TNMC_SHORT_WAITS, the
+    // test of the failure path)
+    const int wait_limit = (d.flags & 8) ? 1 : PIPE_WAIT_LIMIT;
     auto mirrored = [&](int r) { return alternate && r <= L - 2 && ((L - 2 - r) & 1); };
     auto put_site = [&](int r, int c, int a, int b, T e0, T e1) {
         const bool mr = mirrored(r);
@@ -450,7 +459,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
 
     if (tid >= NR) {
         // ================= QR role: waves 2, 3 ==============================
-        RoleSync rs{barQ, perr, redQ, 0};
+        RoleSync rs{barQ, perr, redQ, 0, wait_limit};
         const int q = tid - NR;
         long long cyc_qr = 0, cyc_hh = 0;
         constexpr int CPT = MAXB * MAXB / NR;
@@ -480,9 +489,9 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
             T pre[CPT];
             auto ob = [&](int i) { return rd ? L - i : i; };
             auto fetch_site = [&](int cs) {
-                pipe_wait(prog, need(cs), perr);
-                const int pa0 = dsec[2 * ob(cs)], Dp = pa0 + dsec[2 * ob(cs) + 1];
-                const int pb0 = dsec[2 * ob(cs + 1)], D = pb0 + dsec[2 * ob(cs + 1) + 1];
+                pipe_wait(prog, need(cs), perr, wait_limit);
+                const int pa0 = min((int)dsec[2 * ob(cs)], chi), Dp = min(pa0 + dsec[2 * ob(cs) + 1], chi);
+                const int pb0 = min((int)dsec[2 * ob(cs + 1)], chi), D = min(pb0 + dsec[2 * ob(cs + 1) + 1], chi);
                 const T *os = orow + (size_t)(rd ? L - 1 - cs : cs) * site_sz;
 #pragma unroll
                 for (int i = 0; i < CPT; ++i) {
@@ -495,9 +504,9 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
             fetch_site(0);
             role_sync(rs);   // (mq[0..1])
             for (int c = 0; c < L; ++c) {
-                const int pa0 = dsec[2 * ob(c)], Dp = pa0 + dsec[2 * ob(c) + 1];
-                const int pb0 = dsec[2 * ob(c + 1)], D = pb0 + dsec[2 * ob(c + 1) + 1];
-                const int m0 = mq[2 * c], m1 = mq[2 * c + 1];
+                const int pa0 = min((int)dsec[2 * ob(c)], chi), Dp = min(pa0 + dsec[2 * ob(c) + 1], chi);
+                const int pb0 = min((int)dsec[2 * ob(c + 1)], chi), D = min(pb0 + dsec[2 * ob(c + 1) + 1], chi);
+                const int m0 = min((int)mq[2 * c], chi), m1 = min((int)mq[2 * c + 1], chi);
                 const int K = m0 + m1;
                 double lv0, lv1;
                 lam_of(beta, jrow[c], lv0, lv1);
@@ -538,14 +547,14 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
         if (q == 0) { cycq[0] = cyc_qr; cycq[1] = cyc_hh; }
     } else {
         // ================= SVD role: waves 0, 1 =============================
-        RoleSync rs{barS, perr, redS, 0};
+        RoleSync rs{barS, perr, redS, 0, wait_limit};
         long long cyc_svd = 0, cyc_jac = 0;
         int total_sweeps = 0, maxsweep_hits = 0, redo_f64 = 0;
         const int jac_limit = (d.flags & 2) ? 1 : MAX_SWEEPS;
         double logz_tail = 0.0;
         int done = 0;   // sites finished, over all rows
         for (int r = L - 2; r >= 0; --r) {
-            pipe_wait(qrows, L - 1 - r, perr);
+            pipe_wait(qrows, L - 1 - r, perr, wait_limit);
             const long long ts0 = wall_clock64();
             const unsigned char *mq = mqb + (size_t)(r & 1) * 2 * (L + 1);
             const T *qrow = qscr + (size_t)(r & 1) * qrow_sz;
@@ -554,16 +563,16 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
             role_sync(rs);
             double ulog = 0.0;
             for (int c = L - 1; c >= 0; --c) {
-                const int r0 = dsec[2 * (c + 1)], r1 = dsec[2 * (c + 1) + 1];
+                const int r0 = min((int)dsec[2 * (c + 1)], chi), r1 = min((int)dsec[2 * (c + 1) + 1], chi - r0);
                 const int kr = r0 + r1;
-                const int K0 = mq[2 * c], K1 = mq[2 * c + 1];
+                const int K0 = min((int)mq[2 * c], chi), K1 = min((int)mq[2 * c + 1], chi);
                 const T *qs = qrow + (size_t)c * 4 * cc2;
                 if (c == 0) {
                     double sp = 0.0;
                     for (int m = tid; m < kr; m += NR) {
                         const int p = (m >= r0);
                         const int mm = p ? m - r0 : m;
-                        const int mcq = mq[2 * (c + 1) + p];
+                        const int mcq = min((int)mq[2 * (c + 1) + p], chi);
                         const T *qr = Qst + p * 2 * cc2;
                         const T *xc = X + p * cc2 + mm;
                         T acc = 0, a1 = 0;
@@ -598,7 +607,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                     break;
                 }
                 const int n = (kr + 1) & ~1;
-                const int mn0 = mq[2 * (c + 1)], mn1 = mq[2 * (c + 1) + 1];
+                const int mn0 = min((int)mq[2 * (c + 1)], chi), mn1 = min((int)mq[2 * (c + 1) + 1], chi);
                 if (c == L - 1) {
                     for (int e = tid; e < 2 * n * ldt; e += NR) Tm[(e / (n * ldt)) * bst + e % (n * ldt)] = 0;
                     role_sync(rs);
@@ -656,7 +665,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                     rankv[e] = (v >= (T)0) ? (q0 + q1) + (q2 + q3) : 1 << 20;
                 }
                 // kept columns of block 0 (2n <= 66: the role's threads cover them)
-                const int s0 = (int)role_sum((tid < n && rankv[tid] < kk) ? 1.0 : 0.0, rs);
+                const int s0 = min(max((int)role_sum((tid < n && rankv[tid] < kk) ? 1.0 : 0.0, rs), 0), kk);
                 for (int e = tid; e < 2 * n; e += NR) {
                     if (rankv[e] < kk) {
                         const int p = e / n, re = rankv[e];
@@ -676,7 +685,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                     if (a >= chi || m >= chi) continue;
                     T v0 = 0, v1 = 0;
                     if (a < kk && m < kr) {
-                        const int ce = colof[a], p = ce >> 8, col = ce & 255;
+                        const int ce = colof[a], p = (ce >> 8) & 1, col = min(ce & 255, n);
                         const int pm = m >= r0, mm = pm ? m - r0 : m;
                         const int dp = p ? r1 : r0;
                         const int s = p ^ pm;
@@ -689,7 +698,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                 if (r == 0) {
                     double *u = uvec, *un = uvec + 64;
                     for (int a = tid; a < kk; a += NR) {
-                        const int ce = colof[a], p = ce >> 8, col = ce & 255;
+                        const int ce = colof[a], p = (ce >> 8) & 1, col = min(ce & 255, n);
                         double acc = 0.0;
                         const int dp = p ? r1 : r0, off = p ? r0 : 0;
                         for (int mm = 0; mm < dp; ++mm) acc += (double)Wm[p * bst + col * ldt + mm] * u[off + mm];
@@ -713,7 +722,7 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                     const int Kp = p ? K1 : K0, dp = p ? kk - s0 : s0;
                     if (k < Kp && j < dp) {
                         const int ce = colof[(p ? s0 : 0) + j];
-                        X[p * cc2 + k * chi + j] = Tm[p * bst + (ce & 255) * ldt + k] * inv;
+                        X[p * cc2 + k * chi + j] = Tm[p * bst + min(ce & 255, n) * ldt + k] * inv;
                     }
                 }
                 if (tid == 0) { dsec[2 * c] = (unsigned char)s0; dsec[2 * c + 1] = (unsigned char)(kk - s0); }

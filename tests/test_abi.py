@@ -117,7 +117,8 @@ def test_coupling_kind_is_validated(lib):
 
 
 def test_problem_flags_are_validated(lib):
-    for flags in (T.ALTERNATE_SWEEPS, T.FORCE_F64_FALLBACK, T.ALTERNATE_SWEEPS | T.FORCE_F64_FALLBACK):
+    for flags in (T.ALTERNATE_SWEEPS, T.FORCE_F64_FALLBACK, T.ALTERNATE_SWEEPS | T.FORCE_F64_FALLBACK,
+                  T.ALTERNATE_SWEEPS | T.SHORT_WAITS):
         p = T.Problem(None, None, [8], [8], [1.0], flags=flags)
         assert T.tnmc_workspace_size(p, T.FP32, 8) > 0
     p = T.Problem(None, None, [8], [8], [1.0], flags=4)

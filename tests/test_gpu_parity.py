@@ -422,3 +422,21 @@ def test_pipelined_build_redo_and_reproducibility(G, tnmc):
     _, lq_a, _ = a.sample(16, seed=3)
     _, lq_b, _ = b.sample(16, seed=3)
     assert np.array_equal(np.asarray(lq_a), np.asarray(lq_b))
+
+
+def test_pipelined_build_failure_path_is_reported(G, tnmc):
+    """TNMC_SHORT_WAITS gives every hand-over wait of the row-pipelined build
+    a single poll: the build records the lost hand-over, finishes without
+    waiting (sector sizes clamped, so nothing leaves its buffer), and
+    tnmc_env_check reports TNMC_ENUMERIC for the instance; the same instances
+    built normally are sound."""
+    Js = [workloads.instance(L, "pmj", 50, i) for i, L in enumerate([12, 16])]
+    G.say("pipelined build, failure path (one-poll waits)")
+    bad = G.Run(Js, 16, 1.0, tnmc.FP32, max_samples=4, flags=tnmc.ALTERNATE_SWEEPS | tnmc.SHORT_WAITS)
+    with pytest.raises(tnmc.TnmcError) as e:
+        tnmc.tnmc_env_check(bad.env)
+    assert e.value.code == tnmc.TNMC_ENUMERIC and "hand-over" in str(e.value)
+    assert (bad.stats()[:, tnmc.STAT_PIPE_ERROR] == 1).all()
+    good = G.Run(Js, 16, 1.0, tnmc.FP32, max_samples=4, flags=tnmc.ALTERNATE_SWEEPS)
+    tnmc.tnmc_env_check(good.env)
+    assert (good.stats()[:, tnmc.STAT_PIPE_ERROR] == 0).all()
