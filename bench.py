@@ -453,7 +453,8 @@ def run_paper(args):
     torch.cuda.synchronize()
     log(f"  couplings generated and uploaded in {time.time() - t0:.0f} s (not timed)")
     res = chunked.run(jh, jv, L, chi, beta, T.FP32, N, 0x5A5A0008, budget_bytes=args.budget_gb * 1e9,
-                      coupling_kind=T.COUPLING_PMJ, log=log)
+                      coupling_kind=T.COUPLING_PMJ, log=log,
+                      flags=T.ALTERNATE_SWEEPS if args.sweeps == "alternating" else 0)
     acc, tr = int(res["n_acc"].sum()), int(res["n_trials"].sum())
     per_inst = res["n_acc"] / np.maximum(1, res["n_trials"])
     value = acc / res["wall_s"]
@@ -463,7 +464,8 @@ def run_paper(args):
         "ms_per_step": res["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": value / PAPER_ACCEPTED_PER_S, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"paper run: {B} +-J EA disorders of {L}x{L}, beta {beta}, chi {chi}, {N} samples "
-                               f"each, float32, disorders in chunks of {res['chunks'][0][1]}"},
+                               f"each, float32, {args.sweeps} sweep order, disorders in chunks of "
+                               f"{res['chunks'][0][1]}"},
         "acceptance": acc / max(1, tr),
         "acceptance_per_disorder_mean_sd": [float(per_inst.mean()), float(per_inst.std(ddof=1)) if B > 1 else 0.0],
         "wall_s": res["wall_s"], "build_s": res["build_s"], "sample_s": res["sample_s"],

@@ -20,13 +20,13 @@ from . import (CHAIN_BYTES, COUPLING_GENERAL, Problem, chain_state, tnmc_accept,
 
 
 def plan_chunks(L: int, chi: int, precision: int, n_samples: int, n_inst: int, budget_bytes: float,
-                max_chunk: int = 256):
+                max_chunk: int = 256, flags: int = 0):
     """Largest chunk (at most max_chunk instances) whose workspace and sample
     outputs fit the budget; returns the list of (first, count)."""
     from . import tnmc_workspace_bytes
     per = None
     for k in (1, 2):
-        p = Problem(None, None, [L] * k, chi, 1.0)
+        p = Problem(None, None, [L] * k, chi, 1.0, flags=flags)
         b = tnmc_workspace_bytes(p, precision, n_samples)
         if b == 0:
             raise ValueError("bad chunk problem")
@@ -37,15 +37,17 @@ def plan_chunks(L: int, chi: int, precision: int, n_samples: int, n_inst: int, b
 
 
 def run(J_h, J_v, L: int, chi: int, beta: float, precision: int, n_samples: int, seed: int,
-        budget_bytes: float = 200e9, coupling_kind: int = COUPLING_GENERAL, max_chunk: int = 256, log=None):
+        budget_bytes: float = 200e9, coupling_kind: int = COUPLING_GENERAL, max_chunk: int = 256, log=None,
+        flags: int = 0):
     """J_h (B, L, L-1), J_v (B, L-1, L): device float32 tensors of every
     instance.  Runs build + n_samples draws + energies + Metropolis chain for
     every instance, chunk by chunk.  Returns a dict with per-instance
     accepted / trial counts, mean energy of the chain states, ln Z, the
-    chunk plan and GPU time per phase (hipEvents on the current stream)."""
+    chunk plan and GPU time per phase (hipEvents on the current stream).
+    flags are the problem flags (e.g. ALTERNATE_SWEEPS) of every chunk."""
     import torch
     B = J_h.shape[0]
-    chunks = plan_chunks(L, chi, precision, n_samples, B, budget_bytes, max_chunk)
+    chunks = plan_chunks(L, chi, precision, n_samples, B, budget_bytes, max_chunk, flags)
     stream = torch.cuda.current_stream()
     n_acc = np.zeros(B, np.int64)
     n_tr = np.zeros(B, np.int64)
@@ -56,7 +58,7 @@ def run(J_h, J_v, L: int, chi: int, beta: float, precision: int, n_samples: int,
     for (i0, nb) in chunks:
         jh = J_h[i0:i0 + nb]
         jv = J_v[i0:i0 + nb]
-        p = Problem(jh, jv, [L] * nb, chi, beta, coupling_kind=coupling_kind)
+        p = Problem(jh, jv, [L] * nb, chi, beta, coupling_kind=coupling_kind, flags=flags)
         ws = torch.empty(tnmc_workspace_size(p, precision, n_samples), dtype=torch.uint8, device="cuda")
         spins = torch.empty(n_samples * p.spin_words_per_sample(), dtype=torch.int64, device="cuda")
         logq = torch.empty((nb, n_samples), dtype=torch.float64, device="cuda")
