@@ -44,15 +44,15 @@ TRAFFIC_PROFILE = "profiles/k_build_k_sample_mfma_256x256_chi32_hbm_traffic.txt"
 TRAFFIC = {
     "k_build": {"sources": ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
                             "paper_2509_19006_amd/csrc/build_pipe.hpp", "paper_2509_19006_amd/csrc/device.hpp"],
-                "sha256": "4b7d2fb3ccdeee00aa82f45e885118f55e033c461d51b9c2032fa93a1adae27d",
+                "sha256": "78a742a6923c90148133d6d6dae00bd392234ef172ec1094f7810b5817ebc0c4",
                 "sweeps": "alternating",
-                "bytes": {"fp32": 881139156536, "bf16x3": 881139156536,
-                          "fp16": 795181737288}},
+                "bytes": {"fp32": 879309139358, "bf16x3": 879309139358,
+                          "fp16": 795497683151}},
     "k_sample_mfma": {"sources": ["paper_2509_19006_amd/csrc/sample.hip", "paper_2509_19006_amd/csrc/sample_mfma.hpp",
                                   "paper_2509_19006_amd/csrc/device.hpp"],
                       "sha256": "1602b9d23a3f37cc222099c214d18bb5635cce011dfcf49f1240a5c754ac5939",
-                      "bytes": {"fp32": 1388361258775, "bf16x3": 1388207636577,
-                                "fp16": 1250852210769}},
+                      "bytes": {"fp32": 1388364611354, "bf16x3": 1388216627078,
+                                "fp16": 1250851305618}},
 }
 
 
