@@ -167,6 +167,9 @@ def run_form(T, torch, prec, jh, jv, L, chi, beta, B, N, steps, warmup, seed, fl
     out = dict(value=n_acc / wall, acceptance=n_acc / max(1, n_tr), accepted=n_acc, trials=n_tr,
                wall_s=wall, ms_per_step=1e3 * wall / steps,
                build_ms=phase[0], sample_ms=phase[1], energy_ms=phase[2], accept_ms=phase[3],
+               # the rate once a built cache is reused for further batches of
+               # proposals (no rebuild): sampling, energies and accept only
+               accepted_per_s_cache_reused=n_acc / (steps * 1e-3 * (phase[1] + phase[2] + phase[3])),
                jacobi_sweeps_per_site=float(stats[:, 0].mean()) / ((L - 1) * L),
                build_phase_share=build_phase_share(stats),
                mean_energy_per_spin=float(E.mean().item()) / (L * L),

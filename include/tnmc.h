@@ -166,8 +166,9 @@ typedef struct tnmc_env tnmc_env;   /* opaque; host metadata into workspace */
  * outside the lattice is zero.  Parameters are one float32 vector of
  * TNMC_MLP_NPARAM values, row-major [out][in]:
  *   W1 [64][64] | b1 [64] | W2 [64][64] | b2 [64] | W3 [64] | b3 [1]
- * Inference inside tnmc_sample rounds the weights to bfloat16 and
- * accumulates in float32.                                                 */
+ * Inference inside tnmc_sample runs on the bf16 matrix cores: weights
+ * rounded to bfloat16, activations entering as hi + lo bfloat16 pairs,
+ * float32 accumulation.  Supported with TNMC_FP32 and chi <= 16.          */
 #define TNMC_MLP_IN     64
 #define TNMC_MLP_HIDDEN 64
 #define TNMC_MLP_NPARAM 8385

@@ -12,6 +12,13 @@ constexpr int MLP_IN = 64, MLP_H = 64;
 constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 4096, MLP_OFF_W2 = 4160, MLP_OFF_B2 = 8256;
 constexpr int MLP_OFF_W3 = 8320, MLP_OFF_B3 = 8384, MLP_NPARAM = 8385;
 
+// Learned correction (optional) of a sampling launch: the parameter vector
+// above and the horizontal couplings for the features.
+struct MlpArgs {
+    const float *params;
+    const float *Jh;
+};
+
 // Features of site (r, c): 20 horizontal couplings (rows r-2..r+2, columns
 // c-2..c+1), 20 vertical couplings (rows r-2..r+1, columns c-2..c+2), the
 // 12 already-sampled spins of the 5x5 window (rows r-2, r-1 at c-2..c+2 and

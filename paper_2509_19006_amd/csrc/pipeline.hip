@@ -39,7 +39,6 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
 
     const InstDesc d = desc[inst];
     T *env = reinterpret_cast<T *>(ws + d.env_off);   // one tile's scratch, reused tile after tile
-    const MlpArgs none{nullptr, nullptr};
     const int ntiles = (n_samples + NTS - 1) / NTS;
     for (int tile = 0; tile < ntiles; ++tile) {
         // the sampler form tnmc_sample uses for this instance: float forms
@@ -54,17 +53,17 @@ k_pipeline(const InstDesc *__restrict__ desc, const int32_t *__restrict__ order,
                 sample_tile_mfma<32, S, MODE>(inst, tile, d, ws, fenv, n_samples, sample_seed, sample_offset,
                                               nullptr, spins_out, logq_out, nullptr, Jv_all, smem);
             else if constexpr (MAXB >= 64)
-                sample_tile<T, S, 64, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset,
-                                             nullptr, spins_out, logq_out, nullptr, Jv_all, none,
-                                             reinterpret_cast<typename StageType<T, S>::type(*)[64][64]>(smem), nullptr);
+                sample_tile<T, S, 64>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset,
+                                             nullptr, spins_out, logq_out, nullptr, Jv_all,
+                                             reinterpret_cast<typename StageType<T, S>::type(*)[64][64]>(smem));
         } else if (d.chi <= 16) {
-            sample_tile<T, S, 16, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
-                                         spins_out, logq_out, nullptr, Jv_all, none,
-                                         reinterpret_cast<typename StageType<T, S>::type(*)[16][16]>(smem), nullptr);
+            sample_tile<T, S, 16>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
+                                         spins_out, logq_out, nullptr, Jv_all,
+                                         reinterpret_cast<typename StageType<T, S>::type(*)[16][16]>(smem));
         } else {
-            sample_tile<T, S, 32, false>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
-                                         spins_out, logq_out, nullptr, Jv_all, none,
-                                         reinterpret_cast<typename StageType<T, S>::type(*)[32][32]>(smem), nullptr);
+            sample_tile<T, S, 32>(inst, tile, d, ws, env, n_samples, sample_seed, sample_offset, nullptr,
+                                         spins_out, logq_out, nullptr, Jv_all,
+                                         reinterpret_cast<typename StageType<T, S>::type(*)[32][32]>(smem));
         }
         __syncthreads();
     }

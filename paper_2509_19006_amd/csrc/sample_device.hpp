@@ -8,7 +8,7 @@
 //                (u = the sample's spins of row r-1), rescaled by a power of
 //                two and kept in a per-tile scratch [c][a][sample];
 //   left sweep   l = e_0;  rho_s = |l A_{c,s} R_c|;
-//                logit = ln rho_+ - ln rho_- + 2 beta J_v(r-1,c) u_c (+ MLP);
+//                logit = ln rho_+ - ln rho_- + 2 beta J_v(r-1,c) u_c;
 //                p = sigmoid(logit) in float64; spin = +1 iff Philox u < p
 //                (or the given spin when scoring); log q += ln p or ln(1-p);
 //                l = l A_{c,spin}, rescaled by a power of two.
@@ -17,18 +17,11 @@
 #pragma once
 #include <type_traits>
 
-#include "mlp_device.hpp"
+#include "device.hpp"
 
 namespace tnmc {
 
 constexpr int NTS = 256;
-
-// Learned correction (optional): parameter vector in the layout of
-// mlp_device.hpp and the horizontal couplings for the features.
-struct MlpArgs {
-    const float *params;
-    const float *Jh;
-};
 
 // Element type of the staged sites in shared memory: a float16 cache stays
 // float16 there (half the LDS traffic of the broadcast reads that bound the
@@ -42,15 +35,15 @@ template <typename T, typename ST> __device__ __forceinline__ T sget(ST v) {
 }
 
 // One tile of NTS samples of instance inst (all threads of the workgroup
-// call it).  env: the tile's right-environment scratch; As, Ps: shared
-// arrays for the staged site and the network weights.
-template <typename T, typename S, int CHI, bool HAS_MLP>
+// call it).  env: the tile's right-environment scratch; As: the shared
+// array for the staged site.
+template <typename T, typename S, int CHI>
 __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char *__restrict__ ws, T *env,
                             int n_samples, uint64_t seed, uint64_t sample_offset,
                             const uint64_t *__restrict__ forced, uint64_t *spins_out,
                             double *__restrict__ logq_out, float *__restrict__ logits_out,
-                            const float *__restrict__ Jv_all, MlpArgs mlp,
-                            typename StageType<T, S>::type (*As)[CHI][CHI], float *Ps) {
+                            const float *__restrict__ Jv_all,
+                            typename StageType<T, S>::type (*As)[CHI][CHI]) {
     // no implicit multiply-add fusion: the sampler gives the same bits in
     // every kernel it is inlined into; the contractions fuse explicitly
 #pragma clang fp contract(off)
@@ -69,11 +62,6 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
     float *my_logits = logits_out ? logits_out + (size_t)n_samples * d.site_prefix + (size_t)n * L * L : nullptr;
     const uint32_t sidx = (uint32_t)(sample_offset + (uint64_t)n);
 
-    const float *jh = HAS_MLP ? mlp.Jh + d.off_h : nullptr;
-    if (HAS_MLP) {
-        // weights rounded to bfloat16 (float32 accumulation)
-        for (int e = tid; e < MLP_NPARAM; e += NTS) Ps[e] = __bfloat162float(__float2bfloat16(mlp.params[e]));
-    }
     // Sites are staged through two shared buffers: the next site's entries
     // are fetched into registers before the current site is contracted and
     // stored into the other buffer after it, so one barrier per site
@@ -227,20 +215,6 @@ __device__ void sample_tile(int inst, int tile, const InstDesc &d, unsigned char
                         const double u = (double)((up >> (c & 63)) & 1);
                         logit += 2.0 * beta * (double)jv[(size_t)(r - 1) * L + c] * (2.0 * u - 1.0);
                     }
-                }
-                if (HAS_MLP) {
-                    // spins already fixed: rows above from the output, row r
-                    // from the word being assembled (or the flushed one)
-                    const uint64_t curw = cur;
-                    auto spin = [&](int rr, int cc) -> float {
-                        uint64_t w;
-                        if (rr == r && (cc >> 6) == (c >> 6)) w = curw;
-                        else w = my_out[(size_t)rr * W + (cc >> 6)];
-                        return ((w >> (cc & 63)) & 1) ? 1.f : -1.f;
-                    };
-                    float x[MLP_IN];
-                    mlp_features(jh, jv, L, r, c, spin, (float)logit, x);
-                    logit += (double)mlp_forward(Ps, x);
                 }
                 // sigma(logit) and ln sigma(+-logit) from one exponential:
                 // with e = exp(-|logit|), sigma = 1/(1+e) or e/(1+e) and

@@ -34,10 +34,17 @@
 //            term is below float32 rounding of the result).
 // Right environments go to a per-tile scratch in HBM as float32, in the
 // lanes' own layout, and are read back by the same lanes in the left sweep.
+//
+// Learned correction (MLP = true; chi <= 16, float32): after the TN logit
+// of a site, the network of mlp_device.hpp runs for the wave's 64 samples
+// as two bf16 products per layer with the samples as the column dimension
+// (mlp_site_mfma below), and its output is added to the logit before the
+// draw.
 #pragma once
 #include <type_traits>
 
 #include "device.hpp"
+#include "mlp_device.hpp"
 
 namespace tnmc {
 
@@ -62,7 +69,7 @@ __device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c) {
 }
 
 // Row of the 32 x 32 tile held in result register j of a lane in half h.
-__device__ __forceinline__ constexpr int held_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3); }
+__host__ __device__ constexpr int held_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3); }
 
 // Whether a float32 cache is split into two 16-bit parts (three products).
 template <typename S, int MODE> struct SplitA {
@@ -87,20 +94,169 @@ template <int CHI, typename S, int MODE> __host__ __device__ constexpr size_t mf
 // ... plus the row's vertical-bond tables (two float weights and one double
 // coupling term per column, up to 1024 columns)
 constexpr size_t MF_ROW_TABLE_BYTES = (size_t)16 * 1024;
-template <int CHI, typename S, int MODE> __host__ __device__ constexpr size_t mf_lds_bytes() {
-    return mf_stage_bytes<CHI, S, MODE>() + MF_ROW_TABLE_BYTES;
+
+// ---- the learned correction on the matrix cores ----
+// Weights in shared memory: W1 [o][k] and W2 [o][slot] as bfloat16 rows of
+// MLPW_RS (64 + padding), then b1, b2, W3 and b3 as float32; every value
+// rounded to bfloat16, the rounding every inference of the correction uses.
+constexpr int MLPW_RS = 72;
+constexpr size_t MF_MLP_W_BYTES = (size_t)64 * MLPW_RS * 2;
+constexpr size_t MF_MLP_BYTES = 2 * MF_MLP_W_BYTES + (size_t)(3 * 64 + 4) * 4;
+
+template <int CHI, typename S, int MODE, bool MLP = false> __host__ __device__ constexpr size_t mf_lds_bytes() {
+    return mf_stage_bytes<CHI, S, MODE>() + MF_ROW_TABLE_BYTES + (MLP ? MF_MLP_BYTES : 0);
+}
+
+// Second layer: slot q of lane half h in the 16-wide chunk t of the summed
+// index carries hidden unit mlp_l2_unit(t, h, q), a unit that lane already
+// holds in its first-layer result tiles; W2's columns are staged in that
+// order.
+__host__ __device__ constexpr int mlp_l2_unit(int t, int h, int q) { return 32 * (t >> 1) + held_row(8 * (t & 1) + q, h); }
+
+// tanh x = 1 - 2 / (e^{2x} + 1), the exponential taken in base 2 on the
+// transcendental unit; it saturates to -1 / +1 for large |x|.
+__device__ __forceinline__ float tanh_mc(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // 2 log2(e)
+    return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+}
+
+// Stage the parameter vector P (layout of mlp_device.hpp) into dst; all
+// threads of the workgroup take part, a barrier must follow.
+__device__ __forceinline__ void mlp_stage(const float *__restrict__ P, unsigned char *dst, int tid, int nthr) {
+    __bf16 *w1 = reinterpret_cast<__bf16 *>(dst);
+    __bf16 *w2 = reinterpret_cast<__bf16 *>(dst + MF_MLP_W_BYTES);
+    float *bv = reinterpret_cast<float *>(dst + 2 * MF_MLP_W_BYTES);
+    for (int e = tid; e < MLP_H * MLP_IN; e += nthr) {
+        const int o = e >> 6, k = e & 63;
+        w1[o * MLPW_RS + k] = (__bf16)P[MLP_OFF_W1 + o * MLP_IN + k];
+        w2[o * MLPW_RS + k] = (__bf16)P[MLP_OFF_W2 + o * MLP_H + mlp_l2_unit(k >> 4, (k >> 3) & 1, k & 7)];
+    }
+    for (int e = tid; e < 3 * MLP_H + 1; e += nthr) {
+        const int src = e < 64 ? MLP_OFF_B1 + e : e < 128 ? MLP_OFF_B2 + e - 64 : e < 192 ? MLP_OFF_W3 + e - 128
+                                                                                         : MLP_OFF_B3;
+        bv[e] = (float)(__bf16)P[src];
+    }
+}
+
+// The correction d of the sample whose scalar work this lane carries
+// (column n32 of block h), for all 64 samples of the wave at once.
+//   xc     the site's 40 coupling features (the same for every sample);
+//   sb[nb] spin-feature bits of the sample in column n32 of block nb (bit i
+//          is feature 40 + i: +1 if set, -1 if clear), vm which of those 12
+//          positions lie inside the lattice (feature 0 outside);
+//   xl[nb] that sample's clipped, scaled TN logit (feature 52).
+// Layer 1 takes the features in their natural order (half h of a lane pair
+// supplies inputs 16t + 8h .. 16t + 8h + 7 of chunk t), layer 2 the hidden
+// units each lane holds after layer 1; activations enter as hi + lo bf16
+// pairs, accumulation is float32.  Both lanes of a pair hold half of every
+// hidden vector of both blocks: d needs one exchange, as rho does.
+__device__ __forceinline__ float mlp_site_mfma(const unsigned char *wsm, const float (&xc)[40], const uint32_t (&sb)[2],
+                                               uint32_t vm, const float (&xl)[2], int n32, int h) {
+    const __bf16 *w1 = reinterpret_cast<const __bf16 *>(wsm);
+    const __bf16 *w2 = reinterpret_cast<const __bf16 *>(wsm + MF_MLP_W_BYTES);
+    const float *bv = reinterpret_cast<const float *>(wsm + 2 * MF_MLP_W_BYTES);
+    auto feat = [&](int k, int nb) -> float {
+        if (k < 40) return xc[k];
+        if (k < 52) return ((vm >> (k - 40)) & 1u) ? (((sb[nb] >> (k - 40)) & 1u) ? 1.f : -1.f) : 0.f;
+        return k == 52 ? xl[nb] : 0.f;
+    };
+    f32x16 a1[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) a1[mt][nb][q] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        bf16x8 A[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) A[mt] = *reinterpret_cast<const bf16x8 *>(w1 + (32 * mt + n32) * MLPW_RS + 16 * t + 8 * h);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            bf16x8 bh, bl;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float v = h ? feat(16 * t + 8 + q, nb) : feat(16 * t + q, nb);
+                bh[q] = (__bf16)v;
+                bl[q] = (__bf16)(v - (float)bh[q]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                a1[mt][nb] = mfma16(A[mt], bl, a1[mt][nb]);
+                a1[mt][nb] = mfma16(A[mt], bh, a1[mt][nb]);
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 b = *reinterpret_cast<const float4 *>(bv + 32 * mt + 8 * g + 4 * h);
+            const float bb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a1[mt][nb][4 * g + i] = tanh_mc(a1[mt][nb][4 * g + i] + bb[i]);
+        }
+    f32x16 a2[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) a2[mt][nb][q] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        bf16x8 A[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) A[mt] = *reinterpret_cast<const bf16x8 *>(w2 + (32 * mt + n32) * MLPW_RS + 16 * t + 8 * h);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            bf16x8 bh, bl;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float v = a1[t >> 1][nb][8 * (t & 1) + q];
+                bh[q] = (__bf16)v;
+                bl[q] = (__bf16)(v - (float)bh[q]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                a2[mt][nb] = mfma16(A[mt], bl, a2[mt][nb]);
+                a2[mt][nb] = mfma16(A[mt], bh, a2[mt][nb]);
+            }
+        }
+    }
+    float part[2] = {0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 b = *reinterpret_cast<const float4 *>(bv + 64 + 32 * mt + 8 * g + 4 * h);
+            const float4 w = *reinterpret_cast<const float4 *>(bv + 128 + 32 * mt + 8 * g + 4 * h);
+            const float bb[4] = {b.x, b.y, b.z, b.w}, ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) part[nb] = fmaf(ww[i], tanh_mc(a2[mt][nb][4 * g + i] + bb[i]), part[nb]);
+        }
+    const float mine = h ? part[1] : part[0], other = h ? part[0] : part[1];
+    return (mine + __shfl_xor(other, 32)) + bv[192];
 }
 
 // One tile of 256 samples of instance inst; all 256 threads call it.
 // env: the tile's right-environment scratch (L * CHI * 256 floats).
-// smem: at least mf_lds_bytes<CHI, S, MODE>() bytes, 16-byte aligned.
-template <int CHI, typename S, int MODE>
+// smem: at least mf_lds_bytes<CHI, S, MODE, MLP>() bytes, 16-byte aligned.
+// mlp: the network and the horizontal couplings (MLP only).
+template <int CHI, typename S, int MODE, bool MLP = false>
 __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const unsigned char *__restrict__ ws,
                                  float *__restrict__ env, int n_samples, uint64_t seed, uint64_t sample_offset,
                                  const uint64_t *__restrict__ forced, uint64_t *spins_out,
                                  double *__restrict__ logq_out, float *__restrict__ logits_out,
-                                 const float *__restrict__ Jv_all, unsigned char *smem) {
+                                 const float *__restrict__ Jv_all, unsigned char *smem,
+                                 MlpArgs mlp = MlpArgs{nullptr, nullptr}) {
     static_assert(CHI == 16 || CHI == 32, "matrix-core sampler: chi <= 32");
+    static_assert(!MLP || (CHI == 16 && MODE == MF_F32), "learned correction: chi <= 16, float32");
     using E = typename MfElem<MODE>::E;
     constexpr bool SPLIT = SplitA<S, MODE>::value;
     constexpr int JN = CHI / 2;              // held rows per lane and column block
@@ -131,6 +287,11 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
     // this wave's slice of the scratch: [c][JN * 2 registers][64 lanes]
     float *wenv = env + (size_t)wave * 2 * JN * 64 + l;
     constexpr size_t ENV_C = (size_t)4 * 2 * JN * 64;   // floats per site of the tile
+    // the network's weights (staged here; the first barrier of row 0
+    // precedes their first use)
+    unsigned char *mlp_sm = smem + mf_lds_bytes<CHI, S, MODE>();
+    const float *jh = MLP ? mlp.Jh + d.off_h : nullptr;
+    if constexpr (MLP) mlp_stage(mlp.params, mlp_sm, tid, 256);
 
     // ---- staging, two sites ahead: the entries of site k+2 are fetched
     // into one register set while site k is contracted and site k+1 (fetched
@@ -310,7 +471,7 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
         for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
             for (int j = 0; j < JN; ++j) vec[nb][j] = held_row(j, h) == 0 ? 1.f : 0.f;
-        uint64_t cur = 0, up = 0, fw = 0;
+        uint64_t cur = 0, up = 0, fw = 0, prevw = 0;
         // right environments, one site ahead, through two register sets
         float renvs[2][2][JN];
         auto load_env = [&](auto SET, int c) {
@@ -340,6 +501,47 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             // first, so that its latency hides behind the products
             double u_draw = 0.0;
             if (!my_forced) u_draw = philox_unit(seed, (uint32_t)(r * L + c), sidx, (uint32_t)inst, 0u);
+            // the network's inputs that are already fixed: the site's
+            // couplings and the sample's spins of rows r-2, r-1 (bits 0-9 of
+            // the spin features; vm marks the positions inside the lattice)
+            float xc[40];
+            uint32_t sb_up = 0, vm = 0;
+            if constexpr (MLP) {
+#pragma unroll
+                for (int dr = -2; dr <= 2; ++dr)
+#pragma unroll
+                    for (int dc = -2; dc <= 1; ++dc) {
+                        const int rr = r + dr, cc = c + dc;
+                        xc[(dr + 2) * 4 + dc + 2] =
+                            (rr >= 0 && rr < L && cc >= 0 && cc < L - 1) ? jh[(size_t)rr * (L - 1) + cc] : 0.f;
+                    }
+#pragma unroll
+                for (int dr = -2; dr <= 1; ++dr)
+#pragma unroll
+                    for (int dc = -2; dc <= 2; ++dc) {
+                        const int rr = r + dr, cc = c + dc;
+                        xc[20 + (dr + 2) * 5 + dc + 2] =
+                            (rr >= 0 && rr < L - 1 && cc >= 0 && cc < L) ? jv[(size_t)rr * L + cc] : 0.f;
+                    }
+                const int wl = (c >= 2 ? c - 2 : 0) >> 6, wh = (c + 2 < L ? c + 2 : L - 1) >> 6;
+#pragma unroll
+                for (int dr = -2; dr <= -1; ++dr) {
+                    const int rr = r + dr;
+                    if (rr < 0) continue;
+                    uint64_t wa = 0, wb = 0;
+                    if (act) { wa = my_out[(size_t)rr * W + wl]; wb = my_out[(size_t)rr * W + wh]; }
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) {
+                        const int cc = c - 2 + i, bit = (dr + 2) * 5 + i;
+                        if (cc < 0 || cc >= L) continue;
+                        const uint64_t w = (cc >> 6) == wl ? wa : wb;
+                        sb_up |= (uint32_t)((w >> (cc & 63)) & 1) << bit;
+                        vm |= 1u << bit;
+                    }
+                }
+                if (c >= 2) vm |= 1u << 10;
+                if (c >= 1) vm |= 1u << 11;
+            }
             const E *Ab = stage + buf * SITE;
             // the site's right environment (loaded a step earlier, in this
             // lane's layout); the next site's is fetched now
@@ -443,6 +645,24 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
                     logit += ctab[c] * (2.0 * u - 1.0);
                 }
             }
+            if constexpr (MLP) {
+                // row r's spins at c-2, c-1: in the word being assembled or
+                // in the one flushed last
+                uint32_t sb = sb_up;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int cc = c - 2 + i;
+                    if (cc < 0) continue;
+                    const uint64_t w = (cc >> 6) == (c >> 6) ? cur : prevw;
+                    sb |= (uint32_t)((w >> (cc & 63)) & 1) << (10 + i);
+                }
+                const float xlm = fminf(fmaxf((float)logit, -30.f), 30.f) * 0.125f;
+                const uint32_t sbo = (uint32_t)__shfl_xor((int)sb, 32);
+                const float xlo = __shfl_xor(xlm, 32);
+                const uint32_t sbb[2] = {h ? sbo : sb, h ? sb : sbo};
+                const float xlb[2] = {h ? xlo : xlm, h ? xlm : xlo};
+                logit += (double)mlp_site_mfma(mlp_sm, xc, sbb, vm, xlb, n32, h);
+            }
             const double ex = exp(-fabs(logit));
             const double l1p = log1p(ex);
             int spin;
@@ -457,7 +677,7 @@ __device__ void sample_tile_mfma(int inst, int tile, const InstDesc &d, const un
             if (act) {
                 if (my_logits) my_logits[(size_t)r * L + c] = (float)logit;
                 cur |= (uint64_t)spin << (c & 63);
-                if ((c & 63) == 63 || c == L - 1) { my_out[(size_t)r * W + (c >> 6)] = cur; cur = 0; }
+                if ((c & 63) == 63 || c == L - 1) { my_out[(size_t)r * W + (c >> 6)] = cur; prevw = cur; cur = 0; }
             }
             const int spin_other = __shfl_xor(spin, 32);
             const int sp[2] = {h ? spin_other : spin, h ? spin : spin_other};

@@ -4,7 +4,10 @@ and what the trained network gains over the plain proposal.
 Tolerances: float32 kernels against float64 -- gradients within 2e-4 of
 the largest gradient entry, Adam parameters within 1e-6, forward within
 1e-4 (float32 weights) or 2e-2 relative with cosine >= 0.999 (bfloat16
-weights); features bit-exact (they are copies).
+weights); features bit-exact (they are copies); the sampler's corrected
+logits within 2e-4 of TN logit + the float64 network with the same bfloat16
+weights (its products take the activations as hi + lo bfloat16 pairs, about
+16 significand bits, with float32 accumulation).
 """
 import numpy as np
 import pytest
@@ -84,14 +87,17 @@ def test_forward_matches_oracle(tnmc):
     assert got @ want / (np.linalg.norm(got) * np.linalg.norm(want)) > 0.999
 
 
-def test_features_and_corrected_logits(tnmc):
+@pytest.mark.parametrize("L", [12, 70])
+def test_features_and_corrected_logits(tnmc, L):
     """Features of GPU draws equal the oracle's; with a random network the
-    sampler's corrected logits equal TN logit + oracle MLP (bf16 weights)."""
+    sampler's corrected logits equal TN logit + oracle MLP (bf16 weights).
+    At 70 x 70 the 5 x 5 window crosses the 64-column words of the packed
+    spins."""
     import torch
     import tnmc_gpu as G
-    L, chi, beta, n = 12, 8, 1.0, 24
+    chi, beta, n = 8, 1.0, 24
     Js = [workloads.instance(L, "gauss", 60, i) for i in range(2)]
-    G.say("mlp features + corrected logits, 2 x 12x12 chi 8")
+    G.say(f"mlp features + corrected logits, 2 x {L}x{L} chi 8")
     run = G.Run(Js, chi, beta, tnmc.FP32, max_samples=n)
     P = _rand_params(torch, 5, out_scale=0.2)
     spins = torch.zeros(run.words(n), dtype=torch.int64, device="cuda")
@@ -111,11 +117,14 @@ def test_features_and_corrected_logits(tnmc):
     pb = _params_np(P)
     pb = {k: np.asarray(torch.as_tensor(a).to(torch.bfloat16).to(torch.float64)) for k, a in pb.items()}
     for i, (jh, jv) in enumerate(Js):
-        for (r, c) in [(0, 0), (0, 5), (3, 0), (5, 7), (11, 11), (7, 1)]:
+        sites = [(0, 0), (0, 5), (3, 0), (5, 7), (11, 11), (7, 1)]
+        if L > 64:
+            sites += [(2, 62), (3, 63), (4, 64), (5, 65), (6, 66), (69, 69), (1, 64), (68, 2)]
+        for (r, c) in sites:
             x = mlp.features(sp[i], jh, jv, ltn[i, :, r, c], r, c)
             assert np.array_equal(f[i, :, r, c].astype(np.float64), x.astype(np.float32).astype(np.float64))
             d, _ = mlp.forward(pb, x)
-            assert np.max(np.abs(got[i, :, r, c] - (ltn[i, :, r, c] + d))) < 2e-3
+            assert np.max(np.abs(got[i, :, r, c] - (ltn[i, :, r, c] + d))) < 2e-4
 
 
 def test_zero_network_is_the_plain_proposal(tnmc):
@@ -133,11 +142,11 @@ def test_zero_network_is_the_plain_proposal(tnmc):
         tnmc.tnmc_sample(run.env, n, 17, spins, logq, mlp=m)
         torch.cuda.synchronize()
         out.append((spins.cpu().numpy(), logq.cpu().numpy()))
-    # the plain proposal samples on the matrix cores, the one with the
-    # network on the vector unit (float32 both): draws identical, log q equal
-    # to float32 rounding of the two summation orders
+    # both sample on the matrix cores with the same products and the
+    # network's output is exactly zero: identical draws, log q equal up to
+    # the rounding of the float64 scalar work in two compiled kernels
     assert np.array_equal(out[0][0], out[1][0])
-    assert np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[0][1])) < 2e-5
+    assert np.max(np.abs(out[0][1] - out[1][1]) / np.abs(out[0][1])) < 1e-12
 
 
 def test_selection_falls_back_to_the_plain_proposal(tnmc):
