@@ -46,13 +46,13 @@ TRAFFIC = {
                             "paper_2509_19006_amd/csrc/build_pipe.hpp", "paper_2509_19006_amd/csrc/device.hpp"],
                 "sha256": "78a742a6923c90148133d6d6dae00bd392234ef172ec1094f7810b5817ebc0c4",
                 "sweeps": "alternating",
-                "bytes": {"fp32": 879309139358, "bf16x3": 879309139358,
-                          "fp16": 795497683151}},
+                "bytes": {"fp32": 878966413463, "bf16x3": 878966413463,
+                          "fp16": 795891138461}},
     "k_sample_mfma": {"sources": ["paper_2509_19006_amd/csrc/sample.hip", "paper_2509_19006_amd/csrc/sample_mfma.hpp",
                                   "paper_2509_19006_amd/csrc/device.hpp"],
-                      "sha256": "1602b9d23a3f37cc222099c214d18bb5635cce011dfcf49f1240a5c754ac5939",
-                      "bytes": {"fp32": 1388364611354, "bf16x3": 1388216627078,
-                                "fp16": 1250851305618}},
+                      "sha256": "a278a128d862b30f01e185037317bfba4acf0034e23a2771556e3b82fdb4a25e",
+                      "bytes": {"fp32": 1388362420021, "bf16x3": 1388213317770,
+                                "fp16": 1250852647991}},
 }
 
 
