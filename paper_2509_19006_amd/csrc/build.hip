@@ -57,8 +57,8 @@ size_t build_pipe_lds_bytes(int chi, int L) {
     const size_t cb = chi <= 16 ? 16 : 32;
     const size_t vl = 2 * cb + (64 / cb - 1) * (cb >= 32 ? 4 : 0);   // padded Householder vector
     const size_t bst = (size_t)(chi + 1) * (chi + 1);
-    // QR role: C, R, V, tau; SVD role: Tm, Wm, X, Qst, nrm, Jacobi rotations
-    size_t elems = 3 * cb * cb + 2 * cb * vl + 2 * cb;
+    // QR role: C, R, V, tau, R columns; SVD role: Tm, Wm, X, Qst, nrm, Jacobi rotations
+    size_t elems = 3 * cb * cb + 2 * cb * vl + 2 * cb + 2 * cb * (cb + 4);
     elems += 4 * bst + (size_t)6 * chi * chi + 2 * (chi + 2) + 4 * cb;
     size_t bytes = elems * sizeof(float);
     bytes = (bytes + 7) & ~(size_t)7;

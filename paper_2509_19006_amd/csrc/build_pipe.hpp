@@ -105,9 +105,16 @@ template <int CHI> constexpr int vrow_len_pipe() {
 // column grp of M^p and each lane RR = 2CHI/G consecutive rows.  The
 // reflector of column j goes through shared memory within the wave (no
 // barrier); only the joint norm of R crosses the two waves.
+// Row j of every column becomes final (an entry of R) at step j: it moves to
+// Rs (column-major, row stride CHI + 4, one block per wave) and is zeroed in
+// the registers, so that a column's rows above the current step are always
+// zero.  The pivot's norm is then the sum over all of its rows, the diagonal
+// entry one register at the step's (uniform) index, and the reflector the
+// scaled column with a 1 written over its diagonal entry: no step selects
+// rows by comparing them with the step.
 template <typename T, int CHI>
 __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, int pn0, T lnh0,
-                               T lnh1, const T *C, T *R, T *V, T *tauv, T *qdst, int chi, RoleSync &rs,
+                               T lnh1, const T *C, T *R, T *V, T *tauv, T *Rsc, T *qdst, int chi, RoleSync &rs,
                                int &mc_out, long long &cyc_hh) {
     constexpr int G = 64 / CHI, RR = 2 * CHI / G;
     const int q = threadIdx.x - 128, p = q >> 6, lt = q & 63;
@@ -161,22 +168,22 @@ __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, i
     }
     const long long th0 = wall_clock64();
     const int mc = K < D ? K : D;
+    constexpr int RSL = CHI + 4;
+    T *Rs = Rsc + p * CHI * RSL;
     for (int j = 0; j < mc; ++j) {
         T *vj = V + (p * CHI + j) * VL;
+        // row j sits in the lanes gl == j / RR of every column, at register
+        // j % RR (both uniform)
+        const int jr = j % RR;
+        const bool holds_j = (gl == j / RR);
         if (grp == j) {
-            T x0 = 0, tail[RR];
-#pragma unroll
-            for (int r = 0; r < RR; ++r) {
-                const int row = row0 + r;
-                tail[r] = row > j ? m[r] : (T)0;
-                if (row == j) x0 = m[r];
-            }
-            T s = rows_dot<T, RR>(tail, tail);
-            s = group_sum(s, G);
+            T nr2 = rows_dot<T, RR>(m, m);
+            nr2 = group_sum(nr2, G);
+            T x0 = holds_j ? m[jr] : (T)0;
             x0 = group_sum(x0, G);
             T tj = 0, sc = 0, be = x0;
-            if (s != (T)0) {
-                const T nr2 = x0 * x0 + s;
+            // (below the diagonal all zero: nr2 is x0^2 to the last bit)
+            if (nr2 != x0 * x0) {
                 if (std::is_same<T, float>::value && nr2 >= (T)4.7e-38f) {
                     const T nr = path_sqrt(nr2);
                     be = x0 >= 0 ? -nr : nr;
@@ -190,10 +197,10 @@ __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, i
                 }
             }
 #pragma unroll
-            for (int r = 0; r < RR; ++r) {
-                const int row = row0 + r;
-                vj[vrow0 + r] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
-                m[r] = row < j ? m[r] : (row == j ? be : (T)0);
+            for (int r = 0; r < RR; ++r) vj[vrow0 + r] = m[r] * sc;
+            if (holds_j) {
+                vj[vrow0 + jr] = (T)1;
+                Rs[j * RSL + j] = be;
             }
             if (gl == 0) tauv[p * CHI + j] = tj;
         }
@@ -209,6 +216,11 @@ __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, i
                 w = group_sum(w, G) * tj;
 #pragma unroll
                 for (int r = 0; r < RR; ++r) m[r] -= vr[r] * w;
+            }
+            // row j of this column is final: it moves to Rs
+            if (holds_j) {
+                Rs[grp * RSL + j] = m[jr];
+                m[jr] = (T)0;
             }
         }
     }
@@ -235,11 +247,15 @@ __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, i
         for (int r = 0; r < RR; ++r) if (row0 + r < K) qd[(size_t)(row0 + r) * chi] = qv[r];
     }
     cyc_hh += wall_clock64() - th0;
+    // this column's R entries (rows above and on the diagonal, from Rs)
+    T rv[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) rv[r] = (row0 < CHI) ? Rs[grp * RSL + row0 + r] : (T)0;
     double part = 0.0;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
         const int row = row0 + r;
-        if (row < mc && row <= grp && grp < D) part += (double)m[r] * (double)m[r];
+        if (row < mc && row <= grp && grp < D) part += (double)rv[r] * (double)rv[r];
     }
     // (both blocks' M have been formed from R before this sum's barriers,
     // so R can be overwritten after it)
@@ -250,7 +266,7 @@ __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, i
         const int row = row0 + r;
         const T lam = ((grp >= pn0) != (p == 1)) ? lnh1 : lnh0;
         if (row < CHI)
-            R[rkey_base<CHI, RR>(p * CHI + row) ^ grp] = (row < mc && row <= grp && grp < D) ? (m[r] * inv) * lam : (T)0;
+            R[rkey_base<CHI, RR>(p * CHI + row) ^ grp] = (row < mc && row <= grp && grp < D) ? (rv[r] * inv) * lam : (T)0;
     }
     mc_out = mc;
     return log(nu);
@@ -293,11 +309,13 @@ __device__ __forceinline__ void tform_mfma_pipe(const float *Qs, const float *X,
     }
 }
 
-// svd_redo_f64 for the SVD role (threads 0..127, role barriers).
+// svd_redo_f64 for the SVD role (threads 0..127, role barriers).  The role's
+// barrier state comes by value and its phase goes back as the result (an
+// outlined call then keeps the caller's barrier state in registers).
 template <int MAXB>
-__device__ void svd_redo_f64_pipe(double *fb, const float *q, const float *X, float *Tm, float *Wm, float *nrm,
-                                  int *iflag, int *jflag, int c, int L, int chi, int K0, int K1, int r0, int r1,
-                                  int mn0, int mn1, int n, int kr, int ldt, int bst, RoleSync &rs) {
+__device__ int svd_redo_f64_pipe(double *fb, const float *q, const float *X, float *Tm, float *Wm, float *nrm,
+                                 int *iflag, int *jflag, int c, int L, int chi, int K0, int K1, int r0, int r1,
+                                 int mn0, int mn1, int n, int kr, int ldt, int bst, RoleSync rs) {
     constexpr int NR = 128;
     const int tid = threadIdx.x, cc2 = chi * chi;
     double *Td = fb, *Wd = fb + 2 * bst, *prm = fb + 4 * bst, *nd = prm + 256;
@@ -340,6 +358,7 @@ __device__ void svd_redo_f64_pipe(double *fb, const float *q, const float *X, fl
     }
     for (int e = tid; e < 2 * n; e += NR) nrm[e] = (float)nd[e];
     role_sync(rs);
+    return rs.phase;
 }
 
 // Shared-memory bytes of the pipelined build (float, chi <= 32).
@@ -376,7 +395,8 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
     const int bst = (chi + 1) * ldt;
 
     // ---- shared memory (build_pipe_lds_bytes) ---------------------------
-    // QR role: C [CB][CB], R [2][CB][CB], Vh [2][CB][VL], tau [2][CB]
+    // QR role: C [CB][CB], R [2][CB][CB], Vh [2][CB][VL], tau [2][CB],
+    //          Rsc [2][CB][CB + 4]
     // SVD role: Tm, Wm [2][bst], X [2][chi][chi], Qst [2][2chi][chi],
     //           nrm [2][chi+2], jprm [4CB]
     const int VLb = CB <= 16 ? vrow_len_pipe<16>() : vrow_len_pipe<32>();
@@ -384,7 +404,8 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
     T *R = C + CB * CB;
     T *Vh = R + 2 * CB * CB;
     T *tau = Vh + 2 * CB * VLb;
-    T *Tm = tau + 2 * CB;
+    T *Rsc = tau + 2 * CB;
+    T *Tm = Rsc + 2 * CB * (CB + 4);
     T *Wm = Tm + 2 * bst;
     T *X = Wm + 2 * bst;
     T *Qst = X + 2 * cc2;
@@ -527,10 +548,10 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                 T *qd = qrow + (size_t)c * 4 * cc2;
                 if (chi <= 16)
                     ls += qr_site_pipe<T, 16>(c, c == L - 1, K, D, Dp, pa0, m0, m1, pb0, (T)ln0, (T)ln1, C, R, Vh,
-                                              tau, qd, chi, rs, mc, cyc_hh);
+                                              tau, Rsc, qd, chi, rs, mc, cyc_hh);
                 else
                     ls += qr_site_pipe<T, 32>(c, c == L - 1, K, D, Dp, pa0, m0, m1, pb0, (T)ln0, (T)ln1, C, R, Vh,
-                                              tau, qd, chi, rs, mc, cyc_hh);
+                                              tau, Rsc, qd, chi, rs, mc, cyc_hh);
                 if (c == L - 1) {
                     if (q == 0) { mq[2 * L] = 1; mq[2 * L + 1] = 0; }
                     break;
@@ -629,8 +650,8 @@ __device__ __forceinline__ void build_instance_pipe(int inst, const InstDesc *__
                     const int swm = iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                     total_sweeps += swm;
                     if (swm >= jac_limit) {
-                        svd_redo_f64_pipe<MAXB>(fb, qs, X, Tm, Wm, nrm, iflag, jflag, c, L, chi, K0, K1, r0, r1,
-                                                mn0, mn1, n, kr, ldt, bst, rs);
+                        rs.phase = svd_redo_f64_pipe<MAXB>(fb, qs, X, Tm, Wm, nrm, iflag, jflag, c, L, chi, K0, K1,
+                                                           r0, r1, mn0, mn1, n, kr, ldt, bst, rs);
                         total_sweeps += iflag[0] > iflag[1] ? iflag[0] : iflag[1];
                         ++redo_f64;
                     }
