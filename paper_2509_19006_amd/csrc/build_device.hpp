@@ -311,47 +311,68 @@ __device__ int jacobi_reg(T *Tb, T *Wb, int ld, int K, int n, int lane, int role
             a = pair_sum<IL>(a, G);
             b = pair_sum<IL>(b, G);
             bool rot = false;
-            for (int s = 0; s < CHI; s += 2) {
+            // W takes each step's rotation one step late: its update and
+            // move do not feed the next step's rotation, so they fill the
+            // wait on that step's reduction and square roots
+            T wcs = (T)1, wsn = (T)0;
+            auto w_rotate = [&](auto ODD) {
+                constexpr bool O = decltype(ODD)::value;
 #pragma unroll
-                for (int odd = 0; odd < 2; ++odd) {
-                    T c0 = 0, c1 = 0;
-#pragma unroll
-                    for (int i = 0; i < RK; i += 2) {
-                        c0 += x[i] * y[i];
-                        if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
-                    }
-                    const T c = pair_sum<IL>(c0 + c1, G);
-                    T cs, sn;
-                    rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(odd && last), cs, sn);
-#pragma unroll
-                    for (int i = 0; i < RK; ++i) {
-                        const T u = x[i], v = y[i];
-                        x[i] = cs * u - sn * v;
-                        y[i] = sn * u + cs * v;
-                        const T p = wx[i], q = wy[i];
-                        wx[i] = cs * p - sn * q;
-                        wy[i] = sn * p + cs * q;
-                    }
-                    if (!odd) {
-                        // even -> odd layout: second column from the next group
-#pragma unroll
-                        for (int i = 0; i < RK; ++i) {
-                            y[i] = from_next<IL>(y[i], up);
-                            wy[i] = from_next<IL>(wy[i], up);
-                        }
-                        b = from_next<IL>(b, up);
-                    } else {
-                        // odd -> even layout: first column from the previous
-                        // group (the idle last group has exchanged its two)
-#pragma unroll
-                        for (int i = 0; i < RK; ++i) {
-                            x[i] = from_prev<IL>(x[i], dn);
-                            wx[i] = from_prev<IL>(wx[i], dn);
-                        }
-                        a = from_prev<IL>(a, dn);
-                    }
+                for (int i = 0; i < RK; ++i) {
+                    const T p = wx[i], q = wy[i];
+                    wx[i] = wcs * p - wsn * q;
+                    wy[i] = wsn * p + wcs * q;
                 }
+#pragma unroll
+                for (int i = 0; i < RK; ++i) {
+                    if (!O) wy[i] = from_next<IL>(wy[i], up);
+                    else wx[i] = from_prev<IL>(wx[i], dn);
+                }
+            };
+            // one step; pending: W still owes the previous step (of the
+            // other parity)
+            auto step = [&](auto ODD, bool pending) {
+                constexpr bool O = decltype(ODD)::value;
+                T c0 = 0, c1 = 0;
+#pragma unroll
+                for (int i = 0; i < RK; i += 2) {
+                    c0 += x[i] * y[i];
+                    if (i + 1 < RK) c1 += x[i + 1] * y[i + 1];
+                }
+                const T c = pair_sum<IL>(c0 + c1, G);
+                if (pending) w_rotate(std::integral_constant<bool, !O>{});
+                T cs, sn;
+                rot |= jacobi_rotation<T>(a, b, c, small, tol2, !(O && last), cs, sn);
+#pragma unroll
+                for (int i = 0; i < RK; ++i) {
+                    const T u = x[i], v = y[i];
+                    x[i] = cs * u - sn * v;
+                    y[i] = sn * u + cs * v;
+                }
+                if (!O) {
+                    // even -> odd layout: second column from the next group
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) y[i] = from_next<IL>(y[i], up);
+                    b = from_next<IL>(b, up);
+                } else {
+                    // odd -> even layout: first column from the previous
+                    // group (the idle last group has exchanged its two)
+#pragma unroll
+                    for (int i = 0; i < RK; ++i) x[i] = from_prev<IL>(x[i], dn);
+                    a = from_prev<IL>(a, dn);
+                }
+                wcs = cs;
+                wsn = sn;
+            };
+            using Even = std::integral_constant<bool, false>;
+            using Odd = std::integral_constant<bool, true>;
+            step(Even{}, false);
+            for (int s = 0; s + 2 < CHI; s += 2) {
+                step(Odd{}, true);
+                step(Even{}, true);
             }
+            step(Odd{}, true);
+            w_rotate(Odd{});
             ++sweeps;
             if (__ballot(rot) == 0) break;
         }
