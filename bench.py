@@ -44,15 +44,15 @@ TRAFFIC_PROFILE = "profiles/k_build_k_sample_mfma_256x256_chi32_hbm_traffic.txt"
 TRAFFIC = {
     "k_build": {"sources": ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
                             "paper_2509_19006_amd/csrc/build_pipe.hpp", "paper_2509_19006_amd/csrc/device.hpp"],
-                "sha256": "78a742a6923c90148133d6d6dae00bd392234ef172ec1094f7810b5817ebc0c4",
+                "sha256": "f1c2d1ba2373230d6a680926c56675eaabc9a2a7be89ff37236e60b3ddbc1eca",
                 "sweeps": "alternating",
-                "bytes": {"fp32": 878966413463, "bf16x3": 878966413463,
-                          "fp16": 795891138461}},
+                "bytes": {"fp32": 863380732136, "bf16x3": 863380732136,
+                          "fp16": 781291961714}},
     "k_sample_mfma": {"sources": ["paper_2509_19006_amd/csrc/sample.hip", "paper_2509_19006_amd/csrc/sample_mfma.hpp",
                                   "paper_2509_19006_amd/csrc/device.hpp"],
                       "sha256": "a278a128d862b30f01e185037317bfba4acf0034e23a2771556e3b82fdb4a25e",
-                      "bytes": {"fp32": 1388362420021, "bf16x3": 1388213317770,
-                                "fp16": 1250852647991}},
+                      "bytes": {"fp32": 1388361627638, "bf16x3": 1388209193317,
+                                "fp16": 1250849849525}},
 }
 
 
