@@ -312,6 +312,9 @@ ALT_CASES = [
     ("uneven L fp32", [2, 3, 9, 17], "pmj", 8, 0.7, 1),
     ("24x24 chi32 bf16x3", [24, 23], "gauss", 32, 1.0, 4),
     ("16x16 chi32 fp16", [16, 16], "pmj", 32, 1.0, 3),
+    # bond dimensions that fill neither template's blocks
+    ("21x19 chi24 fp32", [21, 19], "gauss", 24, 1.0, 1),
+    ("14x15 chi12 fp32", [14, 15], "pmj", 12, 0.8, 1),
 ]
 
 
