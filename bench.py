@@ -303,8 +303,8 @@ def run_uneven(args):
     betas = [b for _, _, _, b in spec]
     log(f"uneven batch: {len(spec)} instances, {N} samples each; the library's tuner times the candidate "
         f"schedules on a 1/4-scale sub-lattice replica (objective {args.objective})")
-    cache = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gpurun_out", "tnmc_tuning.txt")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    import tempfile
+    cache = os.path.join(tempfile.gettempdir(), "tnmc_tuning.txt")
     tune = autotune.tune(Js, chis, betas, T.FP32, N, objective=args.objective, scale=4, cache_path=cache)
     cands = ["longest-first", "shortest-first", "as given", "split by bond class"]
     for k, v in zip(cands, tune["candidates_s"]):

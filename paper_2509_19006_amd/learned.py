@@ -129,7 +129,7 @@ def acceptance(Js, chi: int, beta: float, n_samples: int, seed: int, mlp=None):
 
 def select(Js_val, chi: int, beta: float, mlp_params, n_samples: int = 256, seed: int = 11,
            p_max: float = 0.05):
-    """Judge the learned proposal by acceptance on validation disorders.
+    """Select the proposal by acceptance on validation disorders.
 
     Returns (chosen params or None, plain acceptances, learned acceptances):
     the network is kept only if its acceptance beats the plain proposal's,

@@ -23,7 +23,7 @@ def gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def tnmc():
-    """The HIP library binding; on a GPU machine a missing library is an error."""
+    """The HIP library binding; with a GPU present a missing library is an error."""
     if not gpu_available():
         pytest.skip("no GPU visible")
     import paper_2509_19006_amd as lib

@@ -150,7 +150,7 @@ def test_zero_network_is_the_plain_proposal(tnmc):
 
 
 def test_selection_falls_back_to_the_plain_proposal(tnmc):
-    """The acceptance judge keeps a network only on a significant paired win:
+    """The acceptance-based selection keeps a network only on a significant paired win:
     an untrained network with a large random output (a correction that can
     only hurt) is rejected, and the plain proposal's acceptances are what the
     caller then samples with."""
@@ -159,7 +159,7 @@ def test_selection_falls_back_to_the_plain_proposal(tnmc):
     from paper_2509_19006_amd import learned
     L, beta, chi = 16, 1.0, 4
     val_J = [workloads.instance(L, "gauss", 72, i) for i in range(8)]
-    G.say("learned correction: the judge rejects a harmful network")
+    G.say("learned correction: the selection rejects a harmful network")
     P = _rand_params(torch, 9, out_scale=3.0)
     chosen, a0, a1 = learned.select(val_J, chi, beta, P, n_samples=128, seed=12)
     G.say(f"  acceptance plain {a0.mean():.4f}, with the random network {a1.mean():.4f}")
