@@ -87,17 +87,17 @@ def test_forward_matches_oracle(tnmc):
     assert got @ want / (np.linalg.norm(got) * np.linalg.norm(want)) > 0.999
 
 
-@pytest.mark.parametrize("L", [12, 70])
-def test_features_and_corrected_logits(tnmc, L):
+@pytest.mark.parametrize("L,n", [(12, 24), (70, 24), (12, 300)])
+def test_features_and_corrected_logits(tnmc, L, n):
     """Features of GPU draws equal the oracle's; with a random network the
     sampler's corrected logits equal TN logit + oracle MLP (bf16 weights).
     At 70 x 70 the 5 x 5 window crosses the 64-column words of the packed
-    spins."""
+    spins; 300 samples take two tiles of 256, the second mostly idle."""
     import torch
     import tnmc_gpu as G
-    chi, beta, n = 8, 1.0, 24
+    chi, beta = 8, 1.0
     Js = [workloads.instance(L, "gauss", 60, i) for i in range(2)]
-    G.say(f"mlp features + corrected logits, 2 x {L}x{L} chi 8")
+    G.say(f"mlp features + corrected logits, 2 x {L}x{L} chi 8, {n} samples")
     run = G.Run(Js, chi, beta, tnmc.FP32, max_samples=n)
     P = _rand_params(torch, 5, out_scale=0.2)
     spins = torch.zeros(run.words(n), dtype=torch.int64, device="cuda")
