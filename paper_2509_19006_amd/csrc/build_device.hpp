@@ -606,13 +606,21 @@ template <int CHI> constexpr int vrow_len() {
 //   V holds vector j of block p at (p CHI + j) vrow_len, row r of a lane's
 //   segment at its padded offset.
 //   R (mc x D, normalised jointly over both blocks) replaces the R array.
+//   CHI = 64 (float builds only): a lane holds 64 rows, and selecting them
+//   against the step every step spills; there row j of every column moves,
+//   at step j, to Rsc ([2][64][68] floats, column-major, in the workspace)
+//   and is zeroed in the registers, so that a column's rows above the step
+//   are always zero: the pivot takes its diagonal entry out of the registers
+//   at the step's uniform index, the norm of the part below it is the sum
+//   over all rows, and the reflector the scaled column with a 1 written at
+//   the diagonal.
 // At the last site (D = 1) only block 0's single column is written to qdst
 // (the centre of the sweep) and nothing is factored.  Returns ln of the
 // joint norm (0 at the last site) and mc.
 template <typename T, int CHI>
 __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, int pn0, T lnh0,
-                          T lnh1, const T *C, T *R, T *V, T *tauv, T *qdst, int chi, double *red, int &mc_out,
-                          long long &cyc_hh) {
+                          T lnh1, const T *C, T *R, T *V, T *tauv, T *Rsc, T *qdst, int chi, double *red,
+                          int &mc_out, long long &cyc_hh) {
     constexpr int G = 128 / CHI, RR = 2 * CHI / G;
     const int tid = threadIdx.x, p = tid >> 7, lt = tid & 127;
     int grp = lt / G, row0 = (lt % G) * RR;
@@ -670,57 +678,121 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     }
     const long long th0 = wall_clock64();
     const int mc = K < D ? K : D;
-    for (int j = 0; j < mc; ++j) {
-        T *vj = V + (p * CHI + j) * VL;
-        if (grp == j) {
-            T x0 = 0, tail[RR];
+    constexpr bool MOVE_R = CHI == 64;
+    constexpr int RSL = CHI + 4;
+    T *Rs = Rsc + p * CHI * RSL;
+    if constexpr (MOVE_R) {
+        for (int j = 0; j < mc; ++j) {
+            T *vj = V + (p * CHI + j) * VL;
+            // row j sits in the lanes gl == j / RR of every column, at register
+            // j % RR (both uniform)
+            const int jr = j % RR;
+            const bool holds_j = (gl == j / RR);
+            if (grp == j) {
+                // the diagonal entry leaves the registers (this column is done
+                // with them), so that the sum of squares is over the rows below
+                // it alone: a tail far below the diagonal still gets its
+                // reflector
+                T x0 = holds_j ? m[jr] : (T)0;
+                if (holds_j) m[jr] = (T)0;
+                T s = rows_dot<T, RR>(m, m);
+                s = group_sum(s, G);
+                x0 = group_sum(x0, G);
+                T tj = 0, sc = 0, be = x0;
+                if (s != (T)0) {
+                    const T nr2 = x0 * x0 + s;
+                    if (std::is_same<T, float>::value && nr2 >= (T)4.7e-38f) {
+                        const T nr = path_sqrt(nr2);
+                        be = x0 >= 0 ? -nr : nr;
+                        tj = (be - x0) * fast_rcp(be);
+                        sc = fast_rcp(x0 - be);
+                    } else {
+                        const T nr = sqrt(nr2);
+                        be = x0 >= 0 ? -nr : nr;
+                        tj = (be - x0) / be;
+                        sc = (T)1 / (x0 - be);
+                    }
+                }
 #pragma unroll
-            for (int r = 0; r < RR; ++r) {
-                const int row = row0 + r;
-                tail[r] = row > j ? m[r] : (T)0;
-                if (row == j) x0 = m[r];
+                for (int r = 0; r < RR; ++r) vj[vrow0 + r] = m[r] * sc;
+                if (holds_j) {
+                    vj[vrow0 + jr] = (T)1;
+                    Rs[j * RSL + j] = be;
+                }
+                if (gl == 0) tauv[p * CHI + j] = tj;
             }
-            T s = rows_dot<T, RR>(tail, tail);
-            s = group_sum(s, G);
-            x0 = group_sum(x0, G);
-            T tj = 0, sc = 0, be = x0;
-            if (s != (T)0) {
-                const T nr2 = x0 * x0 + s;
-                // float: the hardware's 1-ulp square root and reciprocals
-                // when the column is well inside the normal range (then
-                // |be| and |x0 - be| >= |be| are too: be has the opposite
-                // sign of x0); they read denormal inputs as zero
-                if (std::is_same<T, float>::value && nr2 >= (T)4.7e-38f) {
-                    const T nr = path_sqrt(nr2);
-                    be = x0 >= 0 ? -nr : nr;
-                    tj = (be - x0) * fast_rcp(be);
-                    sc = fast_rcp(x0 - be);
-                } else {
-                    const T nr = sqrt(nr2);
-                    be = x0 >= 0 ? -nr : nr;
-                    tj = (be - x0) / be;
-                    sc = (T)1 / (x0 - be);
+            __syncthreads();
+            if (grp > j) {
+                const T tj = tauv[p * CHI + j];
+                if (tj != (T)0) {
+                    T vr[RR];
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) vr[r] = vj[vrow0 + r];
+                    T w = rows_dot<T, RR>(vr, m);
+                    w = group_sum(w, G) * tj;
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) m[r] -= vr[r] * w;
+                }
+                // row j of this column is final: it moves to Rs
+                if (holds_j) {
+                    Rs[grp * RSL + j] = m[jr];
+                    m[jr] = (T)0;
                 }
             }
-#pragma unroll
-            for (int r = 0; r < RR; ++r) {
-                const int row = row0 + r;
-                vj[vrow0 + r] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
-                m[r] = row < j ? m[r] : (row == j ? be : (T)0);
-            }
-            if (gl == 0) tauv[p * CHI + j] = tj;
         }
-        __syncthreads();
-        if (grp > j) {
-            const T tj = tauv[p * CHI + j];
-            if (tj != (T)0) {
-                T vr[RR];
+    } else {
+        for (int j = 0; j < mc; ++j) {
+            T *vj = V + (p * CHI + j) * VL;
+            if (grp == j) {
+                T x0 = 0, tail[RR];
 #pragma unroll
-                for (int r = 0; r < RR; ++r) vr[r] = vj[vrow0 + r];
-                T w = rows_dot<T, RR>(vr, m);
-                w = group_sum(w, G) * tj;
+                for (int r = 0; r < RR; ++r) {
+                    const int row = row0 + r;
+                    tail[r] = row > j ? m[r] : (T)0;
+                    if (row == j) x0 = m[r];
+                }
+                T s = rows_dot<T, RR>(tail, tail);
+                s = group_sum(s, G);
+                x0 = group_sum(x0, G);
+                T tj = 0, sc = 0, be = x0;
+                if (s != (T)0) {
+                    const T nr2 = x0 * x0 + s;
+                    // float: the hardware's 1-ulp square root and reciprocals
+                    // when the column is well inside the normal range (then
+                    // |be| and |x0 - be| >= |be| are too: be has the opposite
+                    // sign of x0); they read denormal inputs as zero
+                    if (std::is_same<T, float>::value && nr2 >= (T)4.7e-38f) {
+                        const T nr = path_sqrt(nr2);
+                        be = x0 >= 0 ? -nr : nr;
+                        tj = (be - x0) * fast_rcp(be);
+                        sc = fast_rcp(x0 - be);
+                    } else {
+                        const T nr = sqrt(nr2);
+                        be = x0 >= 0 ? -nr : nr;
+                        tj = (be - x0) / be;
+                        sc = (T)1 / (x0 - be);
+                    }
+                }
 #pragma unroll
-                for (int r = 0; r < RR; ++r) m[r] -= vr[r] * w;
+                for (int r = 0; r < RR; ++r) {
+                    const int row = row0 + r;
+                    vj[vrow0 + r] = row < j ? (T)0 : (row == j ? (T)1 : m[r] * sc);
+                    m[r] = row < j ? m[r] : (row == j ? be : (T)0);
+                }
+                if (gl == 0) tauv[p * CHI + j] = tj;
+            }
+            __syncthreads();
+            if (grp > j) {
+                const T tj = tauv[p * CHI + j];
+                if (tj != (T)0) {
+                    T vr[RR];
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) vr[r] = vj[vrow0 + r];
+                    T w = rows_dot<T, RR>(vr, m);
+                    w = group_sum(w, G) * tj;
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) m[r] -= vr[r] * w;
+                }
             }
         }
     }
@@ -749,6 +821,11 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
     // R^p (mc x D, upper trapezoidal), normalised jointly over both blocks
     // and scaled into Rh^p for the next site: column a by lam_h[(a's
     // sector) ^ p] of the next horizontal bond
+    if constexpr (MOVE_R) {
+        // this column's entries come back from Rs
+#pragma unroll
+        for (int r = 0; r < RR; ++r) m[r] = (row0 < CHI) ? Rs[grp * RSL + row0 + r] : (T)0;
+    }
     double part = 0.0;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
@@ -770,14 +847,14 @@ __device__ double qr_site(int c, int last, int K, int D, int Dp, int pa0, int m0
 
 template <typename T, int MAXB>
 __device__ double qr_site_any(int chi, int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, int pn0,
-                              T lnh0, T lnh1, const T *C, T *R, T *V, T *tauv, T *qdst, double *red, int &mc,
-                              long long &cyc_hh) {
-    if (chi <= 16) return qr_site<T, 16>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+                              T lnh0, T lnh1, const T *C, T *R, T *V, T *tauv, T *Rsc, T *qdst, double *red,
+                              int &mc, long long &cyc_hh) {
+    if (chi <= 16) return qr_site<T, 16>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, Rsc, qdst, chi, red, mc, cyc_hh);
     if constexpr (MAXB <= 32) {
-        return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, Rsc, qdst, chi, red, mc, cyc_hh);
     } else {
-        if (chi <= 32) return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
-        return qr_site<T, 64>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, qdst, chi, red, mc, cyc_hh);
+        if (chi <= 32) return qr_site<T, 32>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, Rsc, qdst, chi, red, mc, cyc_hh);
+        return qr_site<T, 64>(c, last, K, D, Dp, pa0, m0, m1, pn0, lnh0, lnh1, C, R, V, tauv, Rsc, qdst, chi, red, mc, cyc_hh);
     }
 }
 
@@ -1108,8 +1185,11 @@ __device__ __forceinline__ void build_instance(int inst, const InstDesc *__restr
             // (b)-(f) in registers: M^p, Householder QR, explicit Q to scratch
             // slot c, normalised and scaled R carried right
             int mc = 1;
+            // (the chi = 64 form's R columns: the float64 redo area after the
+            // Q slots, which only the SVD sweep otherwise uses)
             ls += qr_site_any<T, MAXB>(chi, c, c == L - 1, K, D, Dp, pa0, m0, m1, pb0, (T)ln0, (T)ln1, C, R, Vh,
-                                       tau, qscr + (size_t)c * 4 * cc2, red, mc, cyc_hh);
+                                       tau, qscr + (size_t)L * 4 * cc2, qscr + (size_t)c * 4 * cc2, red, mc,
+                                       cyc_hh);
             if (c == L - 1) {
                 if (tid == 0) { mq[2 * L] = 1; mq[2 * L + 1] = 0; }
                 __syncthreads();

@@ -108,10 +108,11 @@ template <int CHI> constexpr int vrow_len_pipe() {
 // Row j of every column becomes final (an entry of R) at step j: it moves to
 // Rs (column-major, row stride CHI + 4, one block per wave) and is zeroed in
 // the registers, so that a column's rows above the current step are always
-// zero.  The pivot's norm is then the sum over all of its rows, the diagonal
-// entry one register at the step's (uniform) index, and the reflector the
-// scaled column with a 1 written over its diagonal entry: no step selects
-// rows by comparing them with the step.
+// zero.  The pivot takes its diagonal entry out of the registers at the
+// step's (uniform) index; the norm of the part below the diagonal is then
+// the sum over all of its rows, and the reflector the scaled column with a 1
+// written at the diagonal: no step selects rows by comparing them with the
+// step.
 template <typename T, int CHI>
 __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, int m0, int m1, int pn0, T lnh0,
                                T lnh1, const T *C, T *R, T *V, T *tauv, T *Rsc, T *qdst, int chi, RoleSync &rs,
@@ -177,13 +178,18 @@ __device__ double qr_site_pipe(int c, int last, int K, int D, int Dp, int pa0, i
         const int jr = j % RR;
         const bool holds_j = (gl == j / RR);
         if (grp == j) {
-            T nr2 = rows_dot<T, RR>(m, m);
-            nr2 = group_sum(nr2, G);
+            // the diagonal entry leaves the registers (this column is done
+            // with them), so that the sum of squares is over the rows below
+            // it alone: a tail far below the diagonal still gets its
+            // reflector
             T x0 = holds_j ? m[jr] : (T)0;
+            if (holds_j) m[jr] = (T)0;
+            T s = rows_dot<T, RR>(m, m);
+            s = group_sum(s, G);
             x0 = group_sum(x0, G);
             T tj = 0, sc = 0, be = x0;
-            // (below the diagonal all zero: nr2 is x0^2 to the last bit)
-            if (nr2 != x0 * x0) {
+            if (s != (T)0) {
+                const T nr2 = x0 * x0 + s;
                 if (std::is_same<T, float>::value && nr2 >= (T)4.7e-38f) {
                     const T nr = path_sqrt(nr2);
                     be = x0 >= 0 ? -nr : nr;
