@@ -44,15 +44,15 @@ TRAFFIC_PROFILE = "profiles/k_build_k_sample_mfma_256x256_chi32_hbm_traffic.txt"
 TRAFFIC = {
     "k_build": {"sources": ["paper_2509_19006_amd/csrc/build.hip", "paper_2509_19006_amd/csrc/build_device.hpp",
                             "paper_2509_19006_amd/csrc/build_pipe.hpp", "paper_2509_19006_amd/csrc/device.hpp"],
-                "sha256": "f1c2d1ba2373230d6a680926c56675eaabc9a2a7be89ff37236e60b3ddbc1eca",
+                "sha256": "3ebafc8986e3c2de88c256c5a3addda6e41558d7c82014998a7040040b3cac13",
                 "sweeps": "alternating",
-                "bytes": {"fp32": 863380732136, "bf16x3": 863380732136,
-                          "fp16": 781291961714}},
+                "bytes": {"fp32": 863431011740, "bf16x3": 863431011740,
+                          "fp16": 781035878871}},
     "k_sample_mfma": {"sources": ["paper_2509_19006_amd/csrc/sample.hip", "paper_2509_19006_amd/csrc/sample_mfma.hpp",
                                   "paper_2509_19006_amd/csrc/device.hpp"],
                       "sha256": "a278a128d862b30f01e185037317bfba4acf0034e23a2771556e3b82fdb4a25e",
-                      "bytes": {"fp32": 1388361627638, "bf16x3": 1388209193317,
-                                "fp16": 1250849849525}},
+                      "bytes": {"fp32": 1388365171118, "bf16x3": 1388213535742,
+                                "fp16": 1250854359868}},
 }
 
 
