@@ -654,8 +654,8 @@ def main():
                            alternate=args.sweeps == "alternating")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the instances are independent and this build runs "
-              "on a single MI355X; use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the instances are independent and the library runs "
+              "on a single MI355X (see the design notes on sharding); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     cpu_proc = None
